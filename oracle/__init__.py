@@ -51,6 +51,8 @@ def _load():
         lib.oracle_image_band.argtypes = [dp, dp, ctypes.c_int64, ctypes.c_double,
                                           ctypes.c_int, ctypes.c_int, dp, dp, dp]
         lib.oracle_image_band.restype = ctypes.c_int
+        lib.oracle_num_threads.argtypes = []
+        lib.oracle_num_threads.restype = ctypes.c_int
         for name in ("oracle_spline_force", "oracle_spline_potential"):
             f = getattr(lib, name)
             f.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -65,6 +67,11 @@ def _load():
 
 def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def num_threads():
+    """Threads the oracle's parallel loops use."""
+    return int(_load().oracle_num_threads())
 
 
 def spline_force(r, h):

@@ -41,6 +41,10 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <omp.h>
+
+/* number of threads the parallel loops below use */
+int oracle_num_threads(void) { return omp_get_max_threads(); }
 
 /* F(r, h): magnitude of the softened force per unit G m_j (Force_spline_kernel). */
 double oracle_spline_force(double r, double h)
