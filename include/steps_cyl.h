@@ -1,0 +1,127 @@
+/*
+ * steps_cyl.h -- C ABI of the MI355X (gfx950) library for direct-sum gravity
+ * in a domain periodic along z (period L) and open in x and y: the S1 x R2
+ * topology of cylindrical StePS (Sect. 2.1, eq. ForceCylindrical).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - G = 1 and scale factor a = 1 inside force calls: the returned
+ *    acceleration of particle i is
+ *        a_i = sum_{j != i} sum_{n=-n_img}^{n_img} -m_j F(|s|, h_i + h_j) s/|s|,
+ *    s = (x_i - x_j, y_i - y_j, w(z_i - z_j) - n L), with F the cubic-spline
+ *    softened force law (Sect. 2.1, eq. Force_spline_kernel, the pair
+ *    softening h_i + h_j of eq. ComovingEquationsOfMotion) and
+ *    w(t) = t - L floor(t/L + 1/2) the minimum-image separation.  The image
+ *    window |n| <= n_img about the minimum image is the cylinder of
+ *    half-height (n_img + 1/2) L centred on each target (the paper's N_cut
+ *    cut-off read with a half-integer value, identical for i->j and j->i).
+ *    The potential is phi_i = sum m_j P(|s|, h_i + h_j) with dP/dr = F and
+ *    P(inf) = 0, so P = -1/r outside the softening length.
+ *  - Self pairs j == i are excluded, images included.  Coincident distinct
+ *    particles feel no force and contribute P(0) = -2.8 / (h_i + h_j).
+ *  - Particle data are caller-owned DEVICE arrays in structure-of-arrays
+ *    layout: pos = [x_0..x_{N-1} | y_0..y_{N-1} | z_0..z_{N-1}] (FP64, 3N
+ *    doubles), mass[N] >= 0 and eps[N] > 0 (FP64; eps_i is the softening
+ *    length h_i).  z may lie anywhere; it is wrapped into [0, L) in FP64 as
+ *    z - L floor(z/L) before use.  Outputs are caller-owned device arrays.
+ *    The library never frees caller memory and allocates nothing per call
+ *    except where an entry point says otherwise.
+ *  - Every call is asynchronous on `stream` (0 = the null stream); results
+ *    are valid after the stream is synchronised.  Argument errors are found
+ *    on the host before any device work and return a negative status; the
+ *    device data themselves are not validated (NaN/negative masses or
+ *    softenings <= 0 give unspecified, but finite-time, results).
+ *  - No C++ exception crosses this interface.  steps_cyl_last_error() returns
+ *    a message for the last non-OK status of the calling thread.
+ */
+#ifndef STEPS_CYL_H
+#define STEPS_CYL_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STEPS_OK = 0,
+    STEPS_EINVAL = -1,   /* invalid argument (null pointer, size, range)      */
+    STEPS_EDOMAIN = -2,  /* argument outside the supported domain             */
+    STEPS_ENODEV = -3,   /* no usable gfx950 device                           */
+    STEPS_EHIP = -4,     /* a HIP runtime call or kernel launch failed        */
+    STEPS_ENOMEM = -5,   /* allocation failed (network handles only)          */
+    STEPS_EIO = -6       /* file missing, truncated or of the wrong format    */
+} steps_status;
+
+/* Largest image count accepted by the force entry points. */
+#define STEPS_MAX_NIMG 4096
+
+/* Summation modes of steps_cyl_forces_ex. */
+#define STEPS_SUM_COMPENSATED 0   /* FP32 pairs, Kahan-compensated per-target sums */
+#define STEPS_SUM_PLAIN       1   /* FP32 pairs, plain FP32 per-target sums        */
+
+/*
+ * steps_cyl_forces -- exact image-sum accelerations (and potentials) of all N
+ * particles.  Paper: Sect. 2.1, eqs. ComovingEquationsOfMotion (pair sum),
+ * Force_spline_kernel, NewtonianForce and ForceCylindrical.
+ *
+ *   pos      device, 3N doubles, SoA (x | y | z)
+ *   mass     device, N doubles, >= 0
+ *   eps      device, N doubles, > 0 (softening length h_i)
+ *   N        number of particles, 1 <= N <= 2^31 - 1
+ *   L        period along z, finite and > 0
+ *   n_img    images n = -n_img..n_img per pair, 0 <= n_img <= STEPS_MAX_NIMG
+ *   out_acc  device, 3N floats, SoA (a_x | a_y | a_z), written
+ *   out_pot  device, N floats, written; or NULL to skip the potential
+ *   stream   HIP stream
+ *
+ * Arithmetic: pair separations and the z wrap in FP64, then FP32 pair terms
+ * and Kahan-compensated FP32 per-target sums.  Returns STEPS_OK, or
+ * STEPS_EINVAL / STEPS_EHIP.
+ */
+int steps_cyl_forces(const double *pos, const double *mass, const double *eps,
+                     int64_t N, double L, int n_img,
+                     float *out_acc, float *out_pot, hipStream_t stream);
+
+/*
+ * steps_cyl_forces_ex -- as steps_cyl_forces, for a subset of targets and a
+ * chosen summation mode.  Sources are always all N particles.
+ *
+ *   targets    device, n_targets int64 indices in [0, N) (repeats allowed),
+ *              or NULL for every particle (then n_targets must equal N)
+ *   n_targets  number of targets, >= 1
+ *   mode       STEPS_SUM_COMPENSATED or STEPS_SUM_PLAIN
+ *   out_acc    device, 3 * n_targets floats, SoA by target position k
+ *   out_pot    device, n_targets floats or NULL
+ *
+ * Indices outside [0, N) are not checked on the device: the caller owns that
+ * precondition.
+ */
+int steps_cyl_forces_ex(const double *pos, const double *mass, const double *eps,
+                        int64_t N, double L, int n_img,
+                        const int64_t *targets, int64_t n_targets, int mode,
+                        float *out_acc, float *out_pot, hipStream_t stream);
+
+/*
+ * steps_cyl_forces_f64 -- the same sum with every operation in FP64 on the
+ * GPU (a slow reference for precision studies; same definitions, same
+ * arguments as steps_cyl_forces_ex, FP64 outputs).
+ */
+int steps_cyl_forces_f64(const double *pos, const double *mass, const double *eps,
+                         int64_t N, double L, int n_img,
+                         const int64_t *targets, int64_t n_targets,
+                         double *out_acc, double *out_pot, hipStream_t stream);
+
+/* Message for the last non-OK status returned to the calling thread
+ * ("" if none).  The pointer stays valid until the thread's next call. */
+const char *steps_cyl_last_error(void);
+
+/* Library version string. */
+const char *steps_cyl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STEPS_CYL_H */

@@ -1,0 +1,70 @@
+// C entry points of the force sums: host-side argument validation, the
+// device check, and dispatch to the kernels.
+#include "common.h"
+
+namespace steps {
+int launch_forces_exact(const double *pos, const double *mass, const double *eps, int64_t N,
+                        double L, int n_img, const int64_t *targets, int64_t n_tgt, int mode,
+                        float *out_acc, float *out_pot, hipStream_t stream);
+int launch_forces_f64(const double *pos, const double *mass, const double *eps, int64_t N,
+                      double L, int n_img, const int64_t *targets, int64_t n_tgt, double *out_acc,
+                      double *out_pot, hipStream_t stream);
+
+namespace {
+
+int check_common(const void *pos, const void *mass, const void *eps, int64_t N, double L,
+                 int n_img, const void *targets, int64_t n_targets, const void *out_acc) {
+    if (!pos || !mass || !eps) return fail(STEPS_EINVAL, "pos, mass and eps must be non-null");
+    if (!out_acc) return fail(STEPS_EINVAL, "out_acc must be non-null");
+    if (N < 1 || N > INT32_MAX) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^31-1]", (long long)N);
+    if (!finite_positive(L)) return fail(STEPS_EINVAL, "L must be finite and > 0");
+    if (n_img < 0 || n_img > STEPS_MAX_NIMG)
+        return fail(STEPS_EINVAL, "n_img=%d outside [0, %d]", n_img, STEPS_MAX_NIMG);
+    if (n_targets < 1 || n_targets > INT32_MAX)
+        return fail(STEPS_EINVAL, "n_targets=%lld outside [1, 2^31-1]", (long long)n_targets);
+    if (!targets && n_targets != N)
+        return fail(STEPS_EINVAL, "targets is NULL, so n_targets must equal N");
+    return STEPS_OK;
+}
+
+}  // namespace
+}  // namespace steps
+
+using namespace steps;
+
+STEPS_API int steps_cyl_forces(const double *pos, const double *mass, const double *eps, int64_t N,
+                               double L, int n_img, float *out_acc, float *out_pot,
+                               hipStream_t stream) {
+    int rc = check_common(pos, mass, eps, N, L, n_img, nullptr, N, out_acc);
+    if (rc) return rc;
+    if ((rc = require_device())) return rc;
+    clear_error();
+    return launch_forces_exact(pos, mass, eps, N, L, n_img, nullptr, N, STEPS_SUM_COMPENSATED,
+                               out_acc, out_pot, stream);
+}
+
+STEPS_API int steps_cyl_forces_ex(const double *pos, const double *mass, const double *eps,
+                                  int64_t N, double L, int n_img, const int64_t *targets,
+                                  int64_t n_targets, int mode, float *out_acc, float *out_pot,
+                                  hipStream_t stream) {
+    int rc = check_common(pos, mass, eps, N, L, n_img, targets, n_targets, out_acc);
+    if (rc) return rc;
+    if (mode != STEPS_SUM_COMPENSATED && mode != STEPS_SUM_PLAIN)
+        return fail(STEPS_EINVAL, "mode=%d is not a summation mode", mode);
+    if ((rc = require_device())) return rc;
+    clear_error();
+    return launch_forces_exact(pos, mass, eps, N, L, n_img, targets, n_targets, mode, out_acc,
+                               out_pot, stream);
+}
+
+STEPS_API int steps_cyl_forces_f64(const double *pos, const double *mass, const double *eps,
+                                   int64_t N, double L, int n_img, const int64_t *targets,
+                                   int64_t n_targets, double *out_acc, double *out_pot,
+                                   hipStream_t stream) {
+    int rc = check_common(pos, mass, eps, N, L, n_img, targets, n_targets, out_acc);
+    if (rc) return rc;
+    if ((rc = require_device())) return rc;
+    clear_error();
+    return launch_forces_f64(pos, mass, eps, N, L, n_img, targets, n_targets, out_acc, out_pot,
+                             stream);
+}

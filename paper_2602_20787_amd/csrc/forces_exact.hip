@@ -1,0 +1,266 @@
+// Exact image-sum forces on gfx950 (Sect. 2.1, eqs. ComovingEquationsOfMotion,
+// Force_spline_kernel, NewtonianForce, ForceCylindrical).
+//
+// Mapping.  One thread owns one target: its FP64 position, wrapped z and
+// softening stay in registers for the whole launch.  A workgroup of 256
+// threads walks the N sources in tiles of 256; each thread stages one source
+// per tile from the caller's SoA arrays (coalesced FP64 loads), wraps its z
+// into [0, L) in FP64 and writes a 32-byte record {x, y, z, m, h} to LDS.
+// After a barrier every wave reads the tile back by broadcast and runs the
+// pair kernel against its 64 targets.
+//
+// Pair kernel.  Separations and the minimum-image choice are made in FP64
+// (positions up to a few units, clump separations of 1e-3 and below would
+// lose their low bits in FP32), then cast to FP32.  The n = 0 term and the
+// images n = +-1..+-n_img are Newtonian rsqrt terms:
+//   r_n^2 = rho^2 + (d - nL)^2,   S  = sum_n r_n^-3,
+//   U = sum_n n r_n^-3,            Fz = d S - L U = sum_n r_n^-3 (d - nL),
+//   P = sum_n r_n^-1.
+// For |n| >= 2 the pair of images +-n shares C_n = rho^2 + d^2 + n^2 L^2, so
+// r^2_{+-n} = C_n -+ 2 n L d costs 1.5 operations per image; S and U are
+// built as suffix sums over descending n (T += r^-3, U += T), which needs
+// no explicit r^-3 and no per-image weight.  The x and y components factor
+// out of the image sum: a_xy += m_j S (dx, dy).
+// Pairs closer than their softening length h_i + h_j (n = 0 inside the
+// spline core), coincident pairs, the self pair and pairs with
+// h_i + h_j > L/2 (where images could need softening too) take a rare,
+// divergent FP64 branch that evaluates every image with the spline law.
+//
+// Accumulation.  Per target, FP32 partial sums over 32 sources are folded
+// into Kahan-compensated totals (or, in plain mode, every pair is added
+// straight into an FP32 total).
+#include "common.h"
+#include "pair_f64.h"
+
+namespace steps {
+
+namespace {
+
+constexpr int kBlock = 256;  // targets per workgroup and sources per LDS tile
+constexpr int kSub = 32;     // sources per compensated flush
+
+struct alignas(16) SrcRec {
+    double x, y, z;
+    float m, h;
+};
+static_assert(sizeof(SrcRec) == 32, "source record must be 32 bytes");
+
+struct ExactArgs {
+    const double *x, *y, *z, *m, *h;
+    const int64_t *targets;  // null: target k is particle k
+    float *ax, *ay, *az, *pot;
+    double L, invL, halfL;
+    float Lf, L2f, m2Lf;  // L, L^2, -2L in FP32
+    int N, n_tgt, n_img;
+};
+
+// The whole pair in FP64 with the spline law on every image; returns
+// S = sum F(r)/r, Fz = sum F(r)/r (d - nL) and P = -sum P(r).
+struct PairSums {
+    float S, Fz, P;
+};
+
+__device__ __noinline__ PairSums pair_general_f64(double dx, double dy, double d, double h, double L,
+                                                  int n_img) {
+    double s, fz, p;
+    pair_spline_f64(dx, dy, d, h, L, n_img, s, fz, p);
+    return PairSums{(float)s, (float)fz, (float)p};
+}
+
+__device__ __forceinline__ void kahan_add(float &sum, float &c, float x) {
+    const float y = x - c;
+    const float t = sum + y;
+    c = (t - sum) - y;
+    sum = t;
+}
+
+// NIMG >= 0: image count fixed at compile time; NIMG < 0: a.n_img at run time.
+template <int NIMG, bool POT>
+__device__ __forceinline__ void pair_fast(float dx, float dy, float d, const ExactArgs &a,
+                                          float &S, float &Fz, float &P) {
+    const int n_img = (NIMG >= 0) ? NIMG : a.n_img;
+    const float rho2 = __builtin_fmaf(dx, dx, dy * dy);
+    const float r2_0 = __builtin_fmaf(d, d, rho2);
+    const float ri0 = __builtin_amdgcn_rsqf(r2_0);
+    float Tp = 0.f, Tm = 0.f, Up = 0.f, Um = 0.f, Pp = 0.f, Pm = 0.f;
+    if (n_img >= 2) {
+        const float B = d * a.m2Lf;  // -2 L d
+#pragma unroll
+        for (int n = n_img; n >= 2; --n) {
+            const float nf = (float)n;
+            const float Cn = __builtin_fmaf(nf * nf, a.L2f, r2_0);
+            const float r2p = __builtin_fmaf(B, nf, Cn);   // image +n: dz = d - nL
+            const float r2m = __builtin_fmaf(B, -nf, Cn);  // image -n: dz = d + nL
+            const float rip = __builtin_amdgcn_rsqf(r2p);
+            const float rim = __builtin_amdgcn_rsqf(r2m);
+            Tp = __builtin_fmaf(rip * rip, rip, Tp);
+            Tm = __builtin_fmaf(rim * rim, rim, Tm);
+            Up += Tp;
+            Um += Tm;
+            if (POT) {
+                Pp += rip;
+                Pm += rim;
+            }
+        }
+    }
+    if (n_img >= 1) {
+        // n = +-1 directly: the shared-C form would lose ~3 bits here
+        const float dzp = d - a.Lf, dzm = d + a.Lf;
+        const float rip = __builtin_amdgcn_rsqf(__builtin_fmaf(dzp, dzp, rho2));
+        const float rim = __builtin_amdgcn_rsqf(__builtin_fmaf(dzm, dzm, rho2));
+        Tp = __builtin_fmaf(rip * rip, rip, Tp);
+        Tm = __builtin_fmaf(rim * rim, rim, Tm);
+        Up += Tp;
+        Um += Tm;
+        if (POT) {
+            Pp += rip;
+            Pm += rim;
+        }
+    }
+    S = __builtin_fmaf(ri0 * ri0, ri0, Tp + Tm);
+    Fz = __builtin_fmaf(d, S, -a.Lf * (Up - Um));
+    if (POT) P = ri0 + (Pp + Pm);
+}
+
+template <int NIMG, bool POT, bool COMP>
+__global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
+    __shared__ SrcRec tile[kBlock];
+    const int tid = threadIdx.x;
+    const int k = blockIdx.x * kBlock + tid;
+    const bool active = k < a.n_tgt;
+    const int64_t i = active ? (a.targets ? a.targets[k] : (int64_t)k) : 0;
+    const double xi = a.x[i], yi = a.y[i], zi = wrap_z(a.z[i], a.L);
+    const float hi = (float)a.h[i];
+
+    float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;  // totals
+    float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;  // Kahan compensations
+
+    for (int base = 0; base < a.N; base += kBlock) {
+        const int j = base + tid;
+        if (j < a.N) {
+            SrcRec r;
+            r.x = a.x[j];
+            r.y = a.y[j];
+            r.z = wrap_z(a.z[j], a.L);
+            r.m = (float)a.m[j];
+            r.h = (float)a.h[j];
+            tile[tid] = r;
+        }
+        __syncthreads();
+        const int cnt = min(kBlock, a.N - base);
+        for (int s0 = 0; s0 < cnt; s0 += kSub) {
+            const int e = min(kSub, cnt - s0);
+            float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f;
+#pragma unroll 2
+            for (int s = 0; s < e; ++s) {
+                const SrcRec src = tile[s0 + s];
+                const double dx64 = xi - src.x;
+                const double dy64 = yi - src.y;
+                const double t = zi - src.z;
+                const double d64 = min_image(t, a.L, a.invL);
+                const float dx = (float)dx64, dy = (float)dy64, d = (float)d64;
+                const float hij = hi + src.h;
+                float S, Fz, P = 0.f;
+                pair_fast<NIMG, POT>(dx, dy, d, a, S, Fz, P);
+                const float r2_0 = __builtin_fmaf(d, d, __builtin_fmaf(dx, dx, dy * dy));
+                if (r2_0 < hij * hij || hij > (float)a.halfL) {
+                    if ((int64_t)(base + s0 + s) == i) {
+                        S = 0.f;
+                        Fz = 0.f;
+                        P = 0.f;
+                    } else {
+                        const PairSums g = pair_general_f64(dx64, dy64, d64, (double)hi + (double)src.h,
+                                                            a.L, (NIMG >= 0) ? NIMG : a.n_img);
+                        S = g.S;
+                        Fz = g.Fz;
+                        P = g.P;
+                    }
+                }
+                const float mS = src.m * S;
+                if (COMP) {
+                    px = __builtin_fmaf(mS, dx, px);
+                    py = __builtin_fmaf(mS, dy, py);
+                    pz = __builtin_fmaf(src.m, Fz, pz);
+                    if (POT) pp = __builtin_fmaf(src.m, P, pp);
+                } else {
+                    sx = __builtin_fmaf(mS, dx, sx);
+                    sy = __builtin_fmaf(mS, dy, sy);
+                    sz = __builtin_fmaf(src.m, Fz, sz);
+                    if (POT) sp = __builtin_fmaf(src.m, P, sp);
+                }
+            }
+            if (COMP) {
+                kahan_add(sx, cx, px);
+                kahan_add(sy, cy, py);
+                kahan_add(sz, cz, pz);
+                if (POT) kahan_add(sp, cp, pp);
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+        const int n = a.n_tgt;
+        // attraction: a = -sum m_j S (x_i - x_j), potential = -sum m_j / r
+        a.ax[k] = -(sx - cx);
+        a.ay[k] = -(sy - cy);
+        a.az[k] = -(sz - cz);
+        if (POT) a.pot[k] = -(sp - cp);
+        (void)n;
+    }
+}
+
+template <int NIMG, bool POT, bool COMP>
+hipError_t launch_t(const ExactArgs &a, hipStream_t stream) {
+    const int grid = (a.n_tgt + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((forces_exact_kernel<NIMG, POT, COMP>), dim3(grid), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <bool POT, bool COMP>
+hipError_t launch_nimg(const ExactArgs &a, hipStream_t stream) {
+    switch (a.n_img) {
+        case 0: return launch_t<0, POT, COMP>(a, stream);
+        case 1: return launch_t<1, POT, COMP>(a, stream);
+        case 2: return launch_t<2, POT, COMP>(a, stream);
+        case 4: return launch_t<4, POT, COMP>(a, stream);
+        case 8: return launch_t<8, POT, COMP>(a, stream);
+        default: return launch_t<-1, POT, COMP>(a, stream);
+    }
+}
+
+}  // namespace
+
+// Launches the FP32 exact-force kernel; arguments already validated.
+int launch_forces_exact(const double *pos, const double *mass, const double *eps, int64_t N,
+                        double L, int n_img, const int64_t *targets, int64_t n_tgt, int mode,
+                        float *out_acc, float *out_pot, hipStream_t stream) {
+    ExactArgs a;
+    a.x = pos;
+    a.y = pos + N;
+    a.z = pos + 2 * N;
+    a.m = mass;
+    a.h = eps;
+    a.targets = targets;
+    a.ax = out_acc;
+    a.ay = out_acc + n_tgt;
+    a.az = out_acc + 2 * n_tgt;
+    a.pot = out_pot;
+    a.L = L;
+    a.invL = 1.0 / L;
+    a.halfL = 0.5 * L;
+    a.Lf = (float)L;
+    a.L2f = (float)(L * L);
+    a.m2Lf = (float)(-2.0 * L);
+    a.N = (int)N;
+    a.n_tgt = (int)n_tgt;
+    a.n_img = n_img;
+    hipError_t e;
+    const bool comp = (mode == STEPS_SUM_COMPENSATED);
+    if (out_pot)
+        e = comp ? launch_nimg<true, true>(a, stream) : launch_nimg<true, false>(a, stream);
+    else
+        e = comp ? launch_nimg<false, true>(a, stream) : launch_nimg<false, false>(a, stream);
+    return hip_status(e, "forces_exact launch");
+}
+
+}  // namespace steps

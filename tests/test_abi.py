@@ -1,0 +1,100 @@
+"""The C-ABI library loads, exports every entry point its header declares,
+and rejects invalid arguments on the host before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_2602_20787_amd as sc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "steps_cyl.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(steps_cyl_\w+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    assert "steps_cyl_forces" in syms and len(syms) >= 5
+
+
+def test_library_exports_every_declared_symbol():
+    L = sc.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), f"{name} not exported by {sc.library_path}"
+
+
+def test_version_and_error_strings():
+    assert "gfx950" in sc.steps_cyl_version()
+    assert isinstance(sc.steps_cyl_last_error(), str)
+
+
+P = 8  # a non-null dummy address: never dereferenced because validation fails first
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((None, P, P, 10, 1.0, 8, P, None, None), "non-null"),
+    ((P, None, P, 10, 1.0, 8, P, None, None), "non-null"),
+    ((P, P, None, 10, 1.0, 8, P, None, None), "non-null"),
+    ((P, P, P, 10, 1.0, 8, None, None, None), "out_acc"),
+    ((P, P, P, 0, 1.0, 8, P, None, None), "N=0"),
+    ((P, P, P, -5, 1.0, 8, P, None, None), "N=-5"),
+    ((P, P, P, 2 ** 31, 1.0, 8, P, None, None), "N="),
+    ((P, P, P, 10, 0.0, 8, P, None, None), "L must"),
+    ((P, P, P, 10, -1.0, 8, P, None, None), "L must"),
+    ((P, P, P, 10, math.nan, 8, P, None, None), "L must"),
+    ((P, P, P, 10, math.inf, 8, P, None, None), "L must"),
+    ((P, P, P, 10, 1.0, -1, P, None, None), "n_img=-1"),
+    ((P, P, P, 10, 1.0, 4097, P, None, None), "n_img=4097"),
+])
+def test_forces_rejects_invalid_arguments(args, msg):
+    rc = sc.lib().steps_cyl_forces(*args)
+    assert rc == sc.STEPS_EINVAL
+    assert msg in sc.steps_cyl_last_error()
+
+
+@pytest.mark.parametrize("fn", ["steps_cyl_forces_ex", "steps_cyl_forces_f64"])
+def test_subset_entry_points_reject_invalid_arguments(fn):
+    f = getattr(sc.lib(), fn)
+    extra = (0,) if fn == "steps_cyl_forces_ex" else ()
+    # targets NULL but n_targets != N
+    assert f(P, P, P, 10, 1.0, 8, None, 9, *extra, P, None, None) == sc.STEPS_EINVAL
+    assert "n_targets must equal N" in sc.steps_cyl_last_error()
+    # n_targets = 0
+    assert f(P, P, P, 10, 1.0, 8, P, 0, *extra, P, None, None) == sc.STEPS_EINVAL
+    # missing output
+    assert f(P, P, P, 10, 1.0, 8, P, 3, *extra, None, None, None) == sc.STEPS_EINVAL
+
+
+def test_forces_ex_rejects_unknown_mode():
+    rc = sc.lib().steps_cyl_forces_ex(P, P, P, 10, 1.0, 8, None, 10, 7, P, None, None)
+    assert rc == sc.STEPS_EINVAL and "mode=7" in sc.steps_cyl_last_error()
+
+
+def test_no_device_is_reported():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc = sc.lib().steps_cyl_forces(P, P, P, 10, 1.0, 8, P, None, None)
+    assert rc == sc.STEPS_ENODEV
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(sc, "_lib", None)
+    monkeypatch.setattr(sc, "library_path", "/nonexistent/libsteps_cyl.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        sc.lib()
+
+
+def test_binding_checks_tensor_arguments():
+    import torch
+    x = torch.zeros(3, 4, dtype=torch.float64)
+    with pytest.raises(ValueError, match="device"):
+        sc.steps_cyl_forces(x, torch.zeros(4, dtype=torch.float64),
+                            torch.zeros(4, dtype=torch.float64), 1.0, 8)

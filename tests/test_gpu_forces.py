@@ -1,0 +1,208 @@
+"""GPU parity of the exact image-sum kernels against the FP64 oracle.
+
+Bar (stated for the exact path): max over targets of |a_gpu - a_ref| / |a_ref|
+<= 1e-5 for the compensated FP32 kernel, and the same relative bound on the
+potential (all potential terms share one sign, so it has no cancellation).
+The FP64 GPU reference must agree with the oracle to 1e-11 (same definition,
+different operation order).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_ACC = 1e-5
+TOL_POT = 1e-5
+
+
+@pytest.fixture(scope="module")
+def sc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_20787_amd as m
+    return m
+
+
+def to_dev(p):
+    d = torch.device("cuda:0")
+    return (torch.from_numpy(p.pos).to(d), torch.from_numpy(p.mass).to(d),
+            torch.from_numpy(p.eps).to(d))
+
+
+def rel_err(a_gpu, a_ref):
+    a = a_gpu.detach().cpu().numpy().astype(np.float64)
+    num = np.linalg.norm(a - a_ref, axis=0)
+    den = np.linalg.norm(a_ref, axis=0)
+    return num / den
+
+
+def pot_err(p_gpu, p_ref):
+    return np.abs(p_gpu.detach().cpu().numpy().astype(np.float64) - p_ref) / np.abs(p_ref)
+
+
+def run(sc, p, n_img, **kw):
+    pos, m, e = to_dev(p)
+    print(f"[case] N={p.N} n_img={n_img} {kw}", flush=True)
+    acc, pot = sc.steps_cyl_forces(pos, m, e, p.L, n_img, **kw)
+    torch.cuda.synchronize()
+    return acc, pot
+
+
+def test_config1_all_targets(sc):
+    p = synth.cylinder_load(4096, seed=0)
+    acc, pot = run(sc, p, 8)
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8)
+    e = rel_err(acc, a_ref)
+    print(f"C1: max {e.max():.3e} rms {math.sqrt(np.mean(e**2)):.3e}")
+    assert e.max() <= TOL_ACC
+    assert pot_err(pot, p_ref).max() <= TOL_POT
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 255, 256, 257, 1000, 4099])
+def test_ragged_sizes(sc, N):
+    p = synth.cylinder_load(N, seed=N)
+    acc, pot = run(sc, p, 8)
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8)
+    if N == 1:
+        assert torch.all(acc == 0) and torch.all(pot == 0)
+        return
+    assert rel_err(acc, a_ref).max() <= TOL_ACC
+    assert pot_err(pot, p_ref).max() <= TOL_POT
+
+
+@pytest.mark.parametrize("n_img", [0, 1, 2, 3, 4, 5, 8, 16, 64])
+def test_image_counts(sc, n_img):
+    # compile-time image counts (0, 1, 2, 4, 8) and the run-time loop (others)
+    p = synth.cylinder_load(700, seed=5)
+    acc, pot = run(sc, p, n_img)
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, n_img)
+    assert rel_err(acc, a_ref).max() <= TOL_ACC
+    assert pot_err(pot, p_ref).max() <= TOL_POT
+
+
+def test_potential_off_leaves_acceleration_bitwise(sc):
+    p = synth.cylinder_load(1500, seed=7)
+    acc1, _ = run(sc, p, 8)
+    acc2, pot2 = run(sc, p, 8, potential=False)
+    assert pot2 is None
+    assert torch.equal(acc1, acc2)
+
+
+def test_target_subset_is_bitwise_the_full_result(sc):
+    p = synth.cylinder_load(3000, seed=8)
+    pos, m, e = to_dev(p)
+    acc, pot = sc.steps_cyl_forces(pos, m, e, p.L, 8)
+    t = torch.tensor([0, 5, 2999, 5, 1234, 17, 256, 255], dtype=torch.int64, device=pos.device)
+    acc2, pot2 = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t)
+    torch.cuda.synchronize()
+    assert torch.equal(acc2, acc[:, t])
+    assert torch.equal(pot2, pot[t])
+
+
+def test_plain_mode_parity_and_difference(sc):
+    p = synth.cylinder_load(4096, seed=0)
+    pos, m, e = to_dev(p)
+    acc_c, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, mode=sc.STEPS_SUM_COMPENSATED)
+    acc_p, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, mode=sc.STEPS_SUM_PLAIN)
+    torch.cuda.synchronize()
+    a_ref, _ = oracle.forces(p.pos, p.mass, p.eps, p.L, 8)
+    ec, ep = rel_err(acc_c, a_ref), rel_err(acc_p, a_ref)
+    print(f"compensated max {ec.max():.3e}  plain max {ep.max():.3e}")
+    assert ec.max() <= TOL_ACC
+    assert ep.max() <= 1e-4
+    assert not torch.equal(acc_c, acc_p)
+
+
+def test_softened_coincident_and_clumped_pairs(sc):
+    # a tight clump inside the softening lengths, two coincident particles and
+    # a particle exactly on another's axis position
+    base = synth.cylinder_load(900, seed=9)
+    rng = np.random.default_rng(9)
+    pos = base.pos.copy()
+    pos[:, 100:160] = pos[:, 100:101] + 0.002 * rng.standard_normal((3, 60))
+    pos[:, 200] = pos[:, 201]
+    pos[2] = np.mod(pos[2], 1.0)
+    p = synth.Particles(pos, base.mass, base.eps, base.L)
+    acc, pot = run(sc, p, 8)
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8)
+    assert rel_err(acc, a_ref).max() <= TOL_ACC
+    assert pot_err(pot, p_ref).max() <= TOL_POT
+
+
+def test_large_softening_softens_images_too(sc):
+    # h_i + h_j > L/2: the images n != 0 fall inside the spline core
+    p = synth.tiny_load(300, seed=4, box=0.5)
+    eps = np.full(p.N, 0.3)
+    q = synth.Particles(p.pos, p.mass, eps, p.L)
+    acc, pot = run(sc, q, 4)
+    a_ref, p_ref = oracle.forces(q.pos, q.mass, q.eps, q.L, 4)
+    assert rel_err(acc, a_ref).max() <= TOL_ACC
+    assert pot_err(pot, p_ref).max() <= TOL_POT
+
+
+def test_unwrapped_positions_and_other_period(sc):
+    p = synth.tiny_load(600, seed=6, L=2.5, box=1.5)
+    pos = p.pos.copy()
+    pos[2, ::3] += 2.5 * 3
+    pos[2, 1::3] -= 2.5 * 2
+    q = synth.Particles(pos, p.mass, p.eps, 2.5)
+    acc, pot = run(sc, q, 8)
+    a_ref, p_ref = oracle.forces(q.pos, q.mass, q.eps, q.L, 8)
+    assert rel_err(acc, a_ref).max() <= TOL_ACC
+    assert pot_err(pot, p_ref).max() <= TOL_POT
+
+
+def test_deterministic(sc):
+    p = synth.cylinder_load(5000, seed=10)
+    a1, p1 = run(sc, p, 8)
+    a2, p2 = run(sc, p, 8)
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+
+
+def test_f64_reference_matches_oracle(sc):
+    p = synth.cylinder_load(2048, seed=12)
+    pos, m, e = to_dev(p)
+    t = torch.arange(0, 2048, 7, dtype=torch.int64, device=pos.device)
+    acc, pot = sc.steps_cyl_forces_f64(pos, m, e, p.L, 8, targets=t)
+    torch.cuda.synchronize()
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8, targets=t.cpu().numpy())
+    assert rel_err(acc, a_ref).max() <= 1e-11
+    assert pot_err(pot, p_ref).max() <= 1e-12
+
+
+def test_config2_clustered_sampled(sc):
+    p = synth.clustered_load(262144, seed=0)
+    acc, pot = run(sc, p, 8)
+    t = synth.target_sample(p.N, 384, seed=0)
+    # include clump members (the last 83,904 particles are in clumps)
+    t = np.unique(np.concatenate([t, np.arange(p.N - 64, p.N)]))
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8, targets=t)
+    e = rel_err(acc[:, torch.from_numpy(t).cuda()], a_ref)
+    print(f"C2 sampled ({t.size} targets): max {e.max():.3e} rms {math.sqrt(np.mean(e**2)):.3e}")
+    assert e.max() <= TOL_ACC
+    assert pot_err(pot[torch.from_numpy(t).cuda()], p_ref).max() <= TOL_POT
+
+
+def test_config3_full_size_sampled_and_momentum(sc):
+    # the launch the benchmark times: all 2^20 targets, n_img = 8, potential on
+    p = synth.cylinder_load(1 << 20, seed=0)
+    acc, pot = run(sc, p, 8)
+    t = synth.target_sample(p.N, 192, seed=0)
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8, targets=t)
+    tt = torch.from_numpy(t).cuda()
+    e = rel_err(acc[:, tt], a_ref)
+    print(f"C3 sampled: max {e.max():.3e} rms {math.sqrt(np.mean(e**2)):.3e}")
+    assert e.max() <= TOL_ACC
+    assert pot_err(pot[tt], p_ref).max() <= TOL_POT
+    # pair antisymmetry: total momentum change vanishes to round-off
+    a = acc.double().cpu().numpy()
+    mom = np.abs((p.mass[None, :] * a).sum(axis=1))
+    scale = np.sum(p.mass * np.linalg.norm(a, axis=0))
+    print(f"C3 |sum m a| / sum m|a| = {mom.max() / scale:.3e}")
+    assert mom.max() <= 1e-5 * scale

@@ -1,0 +1,179 @@
+"""Pins of the learned-correction oracle: BF16 rounding against the library
+conversion, forward pass against a library network, gradients against
+finite differences, the analytic baseline against quadrature and the exact
+remainder, the symmetry of the folded model, Adam's first step, and the
+antisymmetry of learned pair forces."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import synth
+from oracle import mlp
+
+torch = pytest.importorskip("torch")
+
+
+def test_param_layout_matches_generator():
+    assert mlp.n_params() == 12802 == synth.mlp_param_count()
+    assert [s for _, s in mlp.param_shapes()] == [s for _, s in synth.mlp_param_shapes()]
+
+
+def test_bf16_round_is_round_to_nearest_even():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-6, 6, 10000),
+                        [1.0, -2.5, 1.00390625, 1.01171875, 3.0e-39]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(mlp.bf16_round(x), ref)
+
+
+def _torch_net(params):
+    layers = mlp.unpack(params)
+    mods = []
+    for k, (W, b) in enumerate(layers):
+        lin = torch.nn.Linear(W.shape[1], W.shape[0]).double()
+        lin.weight.data = torch.from_numpy(W)
+        lin.bias.data = torch.from_numpy(b)
+        mods.append(lin)
+        if k < len(layers) - 1:
+            mods.append(torch.nn.SiLU())
+    return torch.nn.Sequential(*mods)
+
+
+def test_forward_matches_library_network():
+    p = synth.mlp_init(seed=3).astype(np.float64)
+    F = np.random.default_rng(1).uniform(-1, 1, (2, 257))
+    out, _ = mlp.forward(p, F)
+    ref = _torch_net(p)(torch.from_numpy(F.T)).detach().numpy().T
+    np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_gradient_matches_finite_differences():
+    rng = np.random.default_rng(2)
+    p = synth.mlp_init(seed=4, out_gain=1.0).astype(np.float64)
+    F = rng.uniform(-1, 1, (2, 64))
+    T = rng.standard_normal((2, 64)) * 0.3
+    _, g = mlp.loss_and_grad(p, F, T)
+    idx = np.concatenate([rng.choice(p.size, 40, replace=False), [0, 191, 192, 12671, 12801]])
+    for i in idx:
+        h = 1e-6
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (mlp.loss_and_grad(pp, F, T)[0] - mlp.loss_and_grad(pm, F, T)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+
+
+def test_gradient_matches_library_autograd():
+    rng = np.random.default_rng(5)
+    p = synth.mlp_init(seed=6, out_gain=1.0).astype(np.float64)
+    F = rng.uniform(-1, 1, (2, 100))
+    T = rng.standard_normal((2, 100))
+    loss, g = mlp.loss_and_grad(p, F, T)
+    net = _torch_net(p)
+    out = net(torch.from_numpy(F.T))
+    lt = ((out - torch.from_numpy(T.T)) ** 2).mean()
+    lt.backward()
+    ref = np.concatenate([t.grad.numpy().ravel() for t in net.parameters()])
+    assert loss == pytest.approx(lt.item(), rel=1e-12)
+    np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-14)
+
+
+def test_rod_part_of_baseline_matches_quadrature():
+    # remove the end corrections: the remaining rod integrals checked by quad
+    for d, r in [(0.0, 0.05), (0.31, 0.7), (0.5, 3.0), (0.12, 19.0)]:
+        def gz(s):
+            u = s - d
+            return u / (u * u + r * r) ** 1.5
+
+        def gr(s):
+            u = s - d
+            return -r / (u * u + r * r) ** 1.5
+        S1, S2 = 1.5, 1024.5
+        qz = sum(integrate.quad(gz, a, b, epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+                 for a, b in [(S1, S2), (-S2, -S1)])
+        qr = sum(integrate.quad(gr, a, b, epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+                 for a, b in [(S1, S2), (-S2, -S1)])
+        bz, br = mlp.baseline(d, r)
+        # end corrections (closed form derivatives at +-1.5) added back by hand
+        cz = cr = 0.0
+        for side in (1.0, -1.0):
+            u = side * 1.5 - d
+            q = (u * u + r * r) ** -2.5
+            cz += side * (r * r - 2 * u * u) * q / 24
+            cr += side * 3 * r * u * q / 24
+        assert float(bz) - cz == pytest.approx(qz, rel=1e-9, abs=1e-13)
+        assert float(br) - cr == pytest.approx(qr, rel=1e-9, abs=1e-13)
+
+
+def test_baseline_approximates_the_exact_remainder():
+    X = synth.remainder_inputs(4096, seed=7)
+    Rz, Rr = mlp.exact_remainder(X[0], X[1])
+    bz, br = mlp.baseline(X[0], X[1])
+    mag = np.hypot(Rz, Rr)
+    res = np.hypot(Rz - bz, Rr - br) / mag
+    assert res.max() < 0.05
+    # the end correction beats the bare rods almost everywhere
+    S1 = 1.5
+    bare_z = bz.copy()
+    bare_r = br.copy()
+    for side in (1.0, -1.0):
+        u = side * S1 - X[0]
+        q = (u * u + X[1] ** 2) ** -2.5
+        bare_z -= side * (X[1] ** 2 - 2 * u * u) * q / 24
+        bare_r -= side * 3 * X[1] * u * q / 24
+    bare = np.hypot(Rz - bare_z, Rr - bare_r) / mag
+    assert np.median(res) < 0.5 * np.median(bare)
+    # far from the axis the images are smooth on the period and the
+    # midpoint rule with its first correction is accurate
+    far = X[1] > 8
+    assert res[far].max() < 1e-4
+
+
+def test_targets_are_order_one():
+    X = synth.remainder_inputs(2048, seed=8)
+    T = mlp.training_targets(X[0], X[1])
+    assert np.all(np.isfinite(T)) and np.abs(T).max() < 2.0 and np.abs(T).std() > 0.01
+
+
+def test_folded_model_symmetry():
+    p = synth.mlp_init(seed=9)
+    d = np.array([0.13, 0.4, 0.02])
+    r = np.array([0.3, 2.0, 11.0])
+    zp, rp = mlp.remainder_model(p, d, r)
+    zm, rm = mlp.remainder_model(p, -d, r)
+    np.testing.assert_array_equal(zp, -zm)
+    np.testing.assert_array_equal(rp, rm)
+
+
+def test_adam_first_step_moves_by_learning_rate():
+    rng = np.random.default_rng(10)
+    p = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    p1, m, v = mlp.adam_step(p, g, np.zeros(50), np.zeros(50), 1, lr=1e-3)
+    # bias-corrected m/sqrt(v) = g/|g| on the first step
+    np.testing.assert_allclose(p1, p - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_learned_pair_forces_are_antisymmetric():
+    p = synth.cylinder_load(96, seed=11)
+    w = synth.mlp_init(seed=12)
+    a = mlp.forces_learned(p.pos, p.mass, p.eps, p.L, w)
+    mom = (p.mass[None, :] * a).sum(axis=1)
+    scale = np.sum(p.mass * np.linalg.norm(a, axis=0))
+    assert np.abs(mom).max() < 1e-13 * scale
+
+
+def test_learned_scheme_with_zero_network_is_near_plus_baseline():
+    p = synth.cylinder_load(64, seed=13)
+    w = np.zeros(mlp.n_params())
+    a = mlp.forces_learned(p.pos, p.mass, p.eps, p.L, w, bf16=False)
+    ref, _ = oracle.forces(p.pos, p.mass, p.eps, p.L, 1024, potential=False)
+    near, _ = oracle.forces(p.pos, p.mass, p.eps, p.L, 1, potential=False)
+    e_learn = np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    e_near = np.linalg.norm(near - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert np.median(e_learn) < 0.2 * np.median(e_near)
