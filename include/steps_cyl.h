@@ -113,6 +113,99 @@ int steps_cyl_forces_f64(const double *pos, const double *mass, const double *ep
                          const int64_t *targets, int64_t n_targets,
                          double *out_acc, double *out_pot, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Learned far-image correction.
+ *
+ * For a pair at minimum-image axial offset d and cylindrical separation rho,
+ * the images 2 <= |n| <= 1024 of eq. ForceCylindrical are replaced by
+ *     R_z   = sign(d) [ b_z(|d|, rho)   + s(rho) o_z ]
+ *     R_rho =           b_rho(|d|, rho) + s(rho) o_rho       (per G m_j / L^2)
+ * where (o_z, o_rho) is a network 2 -> 64 -> 64 -> 64 -> 64 -> 2 (SiLU after
+ * every hidden layer) of the features f1 = 4|d|/L - 1 and
+ * f2 = 2 ln(rho / (0.05 L)) / ln 400 - 1, s(rho) = 0.02 / (1 + (rho/L)^2),
+ * and b is a fixed analytic baseline: the images on each side replaced by a
+ * uniform rod from 1.5 L to 1024.5 L, plus the first midpoint-rule
+ * correction at 1.5 L.  The network domain is 0.05 <= rho/L <= 20; pairs
+ * outside it use the exact image band.  Sign folding makes R_z odd and R_rho
+ * even in d, so learned pair forces stay antisymmetric (momentum is
+ * conserved).  This stands in for the paper's interpolated correction table
+ * D(rho, z) (Sect. 2.2, eq. S1R2EwaldCorrectionTable) as the way to add the
+ * far images to nearest-image forces.
+ *
+ * Parameters: 12802 FP32 values in the order W1 (64x2), b1 (64), W2 (64x64),
+ * b2, W3, b3, W4, b4, W5 (2x64), b5 (2); weights (fan_out, fan_in)
+ * row-major.  Evaluation rounds every weight to BF16 and the inputs of layers
+ * 2-4 to BF16 (round-to-nearest-even); layers 2-4 run on BF16 MFMA with FP32
+ * accumulation, layers 1 and 5 and the activations in FP32.
+ * ---------------------------------------------------------------------- */
+#define STEPS_MLP_PARAMS 12802
+
+typedef struct steps_cyl_mlp steps_cyl_mlp;   /* opaque; owns device memory */
+
+typedef struct {
+    const double *train_in;   /* device [2][n_train]: |d|/L then rho/L (FP64)       */
+    int64_t n_train;          /* a power of two >= 32                               */
+    const double *val_in;     /* device [2][n_val] or NULL                          */
+    int64_t n_val;
+    int64_t steps;            /* optimiser steps                                    */
+    int64_t batch;            /* samples per step, 32 <= batch <= n_train           */
+    float lr, lr_min;         /* cosine schedule from lr (first step) to lr_min     */
+    float beta1, beta2, adam_eps;  /* Adam (Kingma & Ba) hyper-parameters          */
+    uint64_t seed;            /* order of the samples (one permutation per pass)    */
+    int64_t eval_every;       /* record the losses every this many steps (0: never) */
+    float *history;           /* host [3 * history_len]: step, batch loss, val loss */
+    int64_t history_len;
+} steps_cyl_train_cfg;
+
+/* Creates a network from 12802 host FP32 parameters (copied).  Allocates
+ * device memory owned by the handle.  STEPS_EINVAL for null pointers or
+ * non-finite values, STEPS_ENODEV, STEPS_ENOMEM. */
+int steps_cyl_mlp_create(const float *init_params, steps_cyl_mlp **out);
+
+/* Releases the handle and its device memory (NULL is ignored). */
+void steps_cyl_mlp_destroy(steps_cyl_mlp *net);
+
+/* Copies the FP32 master parameters to host_out[12802] (synchronous). */
+int steps_cyl_mlp_get_params(const steps_cyl_mlp *net, float *host_out);
+
+/* Replaces the parameters with host_params[12802] and resets Adam's state
+ * (synchronous). */
+int steps_cyl_mlp_set_params(steps_cyl_mlp *net, const float *host_params);
+
+/* Network outputs for B feature pairs: in = device [2][B] FP32 (f1 | f2),
+ * out = device [2][B] FP32 (o_z | o_rho). */
+int steps_cyl_mlp_forward(const steps_cyl_mlp *net, const float *in, float *out, int64_t B,
+                          hipStream_t stream);
+
+/* Loss mean((o - target)^2) over both outputs of B samples and its gradient
+ * with respect to the FP32 master parameters: in, target = device [2][B]
+ * FP32, grad_out = device [12802] FP32, loss_out = device float or NULL.
+ * Allocates per-call scratch ((B/32) x 12802 floats) and synchronises the
+ * stream before returning.  1 <= B <= 2^24. */
+int steps_cyl_mlp_grad(const steps_cyl_mlp *net, const float *in, const float *target, int64_t B,
+                       float *grad_out, float *loss_out, hipStream_t stream);
+
+/* Training samples: for in = device [2][n] FP64 (|d|/L, rho/L), writes the
+ * features (device [2][n] FP32) and the fit targets (exact band - baseline)/s
+ * (device [2][n] FP32), the band summed in FP64. */
+int steps_cyl_mlp_samples(const double *in, int64_t n, float *features, float *targets,
+                          hipStream_t stream);
+
+/* Trains the network with Adam on minibatches of the samples generated from
+ * cfg->train_in.  Allocates its scratch for the call and synchronises the
+ * stream before returning.  Not thread-safe on one handle. */
+int steps_cyl_mlp_train(steps_cyl_mlp *net, const steps_cyl_train_cfg *cfg, hipStream_t stream);
+
+/* Saves the FP32 master parameters: 8-byte magic "SCYLMLP1", uint32 format
+ * version 1, uint32 parameter count, the parameters, a 64-bit FNV-1a
+ * checksum of them.  STEPS_EIO on write errors. */
+int steps_cyl_mlp_save(const steps_cyl_mlp *net, const char *path);
+
+/* Loads a file written by steps_cyl_mlp_save into a new handle.  STEPS_EIO
+ * for a missing, truncated, oversized or corrupt file (magic, version, count
+ * or checksum), before any device allocation. */
+int steps_cyl_mlp_load(const char *path, steps_cyl_mlp **out);
+
 /* Message for the last non-OK status returned to the calling thread
  * ("" if none).  The pointer stays valid until the thread's next call. */
 const char *steps_cyl_last_error(void);

@@ -175,7 +175,11 @@ def loss_and_grad(params, F, T, bf16=False):
     """Loss mean((o - T)^2) over both outputs and all samples, and its
     gradient with respect to the flat parameter vector.  With ``bf16`` the
     forward pass uses the rounded weights and activations and the backward
-    pass treats each rounding as the identity (straight-through)."""
+    pass treats each rounding as the identity (straight-through); the
+    matrix products of layers 2-4 then take BF16-rounded pre-activation
+    gradients, as BF16 matrix units do (dW = bf16(dz) x^T and the propagated
+    gradient W^T bf16(dz)), while bias gradients and layers 1 and 5 use the
+    unrounded values."""
     out, cache = forward(params, F, bf16)
     T = np.asarray(T, dtype=np.float64)
     n = T.shape[1]
@@ -186,10 +190,11 @@ def loss_and_grad(params, F, T, bf16=False):
     for k in range(DEPTH, -1, -1):
         x_in, Wq, z = cache[k]
         dz = g if k == DEPTH else g * silu_grad(z)
-        dW = dz @ x_in.T
+        dzq = bf16_round(dz) if (bf16 and 1 <= k <= DEPTH - 1) else dz
+        dW = dzq @ x_in.T
         db = dz.sum(axis=1)
         grads.append((dW, db))
-        g = Wq.T @ dz
+        g = Wq.T @ dzq
     grads.reverse()
     flat = np.concatenate([np.concatenate([dW.ravel(), db.ravel()]) for dW, db in grads])
     return loss, flat

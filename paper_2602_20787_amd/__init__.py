@@ -15,7 +15,11 @@ __all__ = [
     "StepsError", "lib", "library_path",
     "steps_cyl_forces", "steps_cyl_forces_ex", "steps_cyl_forces_f64",
     "steps_cyl_last_error", "steps_cyl_version",
-    "STEPS_SUM_COMPENSATED", "STEPS_SUM_PLAIN", "STEPS_MAX_NIMG",
+    "STEPS_SUM_COMPENSATED", "STEPS_SUM_PLAIN", "STEPS_MAX_NIMG", "STEPS_MLP_PARAMS",
+    "steps_cyl_mlp_create", "steps_cyl_mlp_destroy", "steps_cyl_mlp_get_params",
+    "steps_cyl_mlp_set_params", "steps_cyl_mlp_forward", "steps_cyl_mlp_grad",
+    "steps_cyl_mlp_samples", "steps_cyl_mlp_train", "steps_cyl_mlp_save", "steps_cyl_mlp_load",
+    "Mlp",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -33,6 +37,7 @@ STATUS_NAMES = {0: "STEPS_OK", -1: "STEPS_EINVAL", -2: "STEPS_EDOMAIN", -3: "STE
 STEPS_SUM_COMPENSATED = 0
 STEPS_SUM_PLAIN = 1
 STEPS_MAX_NIMG = 4096
+STEPS_MLP_PARAMS = 12802
 
 
 class StepsError(RuntimeError):
@@ -47,10 +52,34 @@ _I64 = ctypes.c_int64
 _I32 = ctypes.c_int
 _F64 = ctypes.c_double
 
+class TrainCfg(ctypes.Structure):
+    """Mirror of steps_cyl_train_cfg."""
+    _fields_ = [
+        ("train_in", ctypes.c_void_p), ("n_train", ctypes.c_int64),
+        ("val_in", ctypes.c_void_p), ("n_val", ctypes.c_int64),
+        ("steps", ctypes.c_int64), ("batch", ctypes.c_int64),
+        ("lr", ctypes.c_float), ("lr_min", ctypes.c_float),
+        ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
+        ("seed", ctypes.c_uint64), ("eval_every", ctypes.c_int64),
+        ("history", ctypes.c_void_p), ("history_len", ctypes.c_int64),
+    ]
+
+
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
 _SIGNATURES = {
     "steps_cyl_forces": [_VP, _VP, _VP, _I64, _F64, _I32, _VP, _VP, _VP],
     "steps_cyl_forces_ex": [_VP, _VP, _VP, _I64, _F64, _I32, _VP, _I64, _I32, _VP, _VP, _VP],
     "steps_cyl_forces_f64": [_VP, _VP, _VP, _I64, _F64, _I32, _VP, _I64, _VP, _VP, _VP],
+    "steps_cyl_mlp_create": [_VP, _PP],
+    "steps_cyl_mlp_get_params": [_VP, _VP],
+    "steps_cyl_mlp_set_params": [_VP, _VP],
+    "steps_cyl_mlp_forward": [_VP, _VP, _VP, _I64, _VP],
+    "steps_cyl_mlp_grad": [_VP, _VP, _VP, _I64, _VP, _VP, _VP],
+    "steps_cyl_mlp_samples": [_VP, _I64, _VP, _VP, _VP],
+    "steps_cyl_mlp_train": [_VP, ctypes.POINTER(TrainCfg), _VP],
+    "steps_cyl_mlp_save": [_VP, ctypes.c_char_p],
+    "steps_cyl_mlp_load": [ctypes.c_char_p, _PP],
 }
 
 
@@ -66,6 +95,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
+        L.steps_cyl_mlp_destroy.argtypes = [_VP]
+        L.steps_cyl_mlp_destroy.restype = None
         L.steps_cyl_last_error.restype = ctypes.c_char_p
         L.steps_cyl_last_error.argtypes = []
         L.steps_cyl_version.restype = ctypes.c_char_p
@@ -169,3 +200,156 @@ def steps_cyl_forces_f64(pos, mass, eps, L, n_img, targets=None, out_acc=None, o
     _check(lib().steps_cyl_forces_f64(p_pos, p_m, p_e, N, float(L), int(n_img), p_t, T, p_acc,
                                       p_pot, _stream(stream, pos.device)))
     return out_acc, (out_pot if potential else None)
+
+
+# ---------------------------------------------------------------- network
+def _host_f32(a, n, name):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != n:
+        raise ValueError(f"{name} must hold {n} values")
+    return a
+
+
+def steps_cyl_mlp_create(init_params):
+    """Handle (int) of a network made from 12802 host parameters."""
+    p = _host_f32(init_params, STEPS_MLP_PARAMS, "init_params")
+    h = ctypes.c_void_p()
+    _check(lib().steps_cyl_mlp_create(p.ctypes.data, ctypes.byref(h)))
+    return h.value
+
+
+def steps_cyl_mlp_destroy(handle):
+    if handle:
+        lib().steps_cyl_mlp_destroy(handle)
+
+
+def steps_cyl_mlp_get_params(handle):
+    import numpy as np
+    out = np.empty(STEPS_MLP_PARAMS, dtype=np.float32)
+    _check(lib().steps_cyl_mlp_get_params(handle, out.ctypes.data))
+    return out
+
+
+def steps_cyl_mlp_set_params(handle, params):
+    p = _host_f32(params, STEPS_MLP_PARAMS, "params")
+    _check(lib().steps_cyl_mlp_set_params(handle, p.ctypes.data))
+
+
+def steps_cyl_mlp_forward(handle, features, out=None, stream=None):
+    """Outputs (2, B) FP32 for device features (2, B) FP32."""
+    import torch
+    B = features.shape[1]
+    p_in = _dev(features, torch.float32, "features", 2 * B)
+    if out is None:
+        out = torch.empty((2, B), dtype=torch.float32, device=features.device)
+    p_out = _dev(out, torch.float32, "out", 2 * B)
+    _check(lib().steps_cyl_mlp_forward(handle, p_in, p_out, B, _stream(stream, features.device)))
+    return out
+
+
+def steps_cyl_mlp_grad(handle, features, targets, stream=None):
+    """(gradient (12802,) FP32, loss () FP32) on device for one batch."""
+    import torch
+    B = features.shape[1]
+    p_in = _dev(features, torch.float32, "features", 2 * B)
+    p_t = _dev(targets, torch.float32, "targets", 2 * B)
+    g = torch.empty((STEPS_MLP_PARAMS,), dtype=torch.float32, device=features.device)
+    loss = torch.empty((), dtype=torch.float32, device=features.device)
+    _check(lib().steps_cyl_mlp_grad(handle, p_in, p_t, B, g.data_ptr(), loss.data_ptr(),
+                                    _stream(stream, features.device)))
+    return g, loss
+
+
+def steps_cyl_mlp_samples(inputs, stream=None):
+    """(features, targets), each (2, n) FP32, for device inputs (2, n) FP64
+    holding |d|/L and rho/L."""
+    import torch
+    n = inputs.shape[1]
+    p_in = _dev(inputs, torch.float64, "inputs", 2 * n)
+    F = torch.empty((2, n), dtype=torch.float32, device=inputs.device)
+    T = torch.empty((2, n), dtype=torch.float32, device=inputs.device)
+    _check(lib().steps_cyl_mlp_samples(p_in, n, F.data_ptr(), T.data_ptr(),
+                                       _stream(stream, inputs.device)))
+    return F, T
+
+
+def steps_cyl_mlp_train(handle, train_in, steps, batch, lr=1e-3, lr_min=1e-5, beta1=0.9,
+                        beta2=0.999, adam_eps=1e-8, seed=0, val_in=None, eval_every=0,
+                        stream=None):
+    """Adam training on device inputs (2, n) FP64; returns the recorded
+    history as an (k, 3) array of (step, batch loss, validation loss)."""
+    import numpy as np
+    import torch
+    n = train_in.shape[1]
+    cfg = TrainCfg()
+    cfg.train_in = _dev(train_in, torch.float64, "train_in", 2 * n)
+    cfg.n_train = n
+    if val_in is not None:
+        cfg.val_in = _dev(val_in, torch.float64, "val_in")
+        cfg.n_val = val_in.shape[1]
+    cfg.steps, cfg.batch = int(steps), int(batch)
+    cfg.lr, cfg.lr_min = float(lr), float(lr_min)
+    cfg.beta1, cfg.beta2, cfg.adam_eps = float(beta1), float(beta2), float(adam_eps)
+    cfg.seed = int(seed)
+    cfg.eval_every = int(eval_every)
+    k = (int(steps) // int(eval_every) + 1) if eval_every else 0
+    hist = np.zeros((max(k, 1), 3), dtype=np.float32)
+    cfg.history = hist.ctypes.data if k else None
+    cfg.history_len = k
+    _check(lib().steps_cyl_mlp_train(handle, ctypes.byref(cfg), _stream(stream, train_in.device)))
+    return hist[: (hist[:, 0] > 0).sum()] if k else hist[:0]
+
+
+def steps_cyl_mlp_save(handle, path):
+    _check(lib().steps_cyl_mlp_save(handle, os.fsencode(path)))
+
+
+def steps_cyl_mlp_load(path):
+    h = ctypes.c_void_p()
+    _check(lib().steps_cyl_mlp_load(os.fsencode(path), ctypes.byref(h)))
+    return h.value
+
+
+class Mlp:
+    """Owning wrapper of a network handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    @classmethod
+    def create(cls, params):
+        return cls(steps_cyl_mlp_create(params))
+
+    @classmethod
+    def load(cls, path):
+        return cls(steps_cyl_mlp_load(path))
+
+    def close(self):
+        if self.handle:
+            steps_cyl_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        return steps_cyl_mlp_get_params(self.handle)
+
+    def set_params(self, p):
+        steps_cyl_mlp_set_params(self.handle, p)
+
+    def forward(self, features, **kw):
+        return steps_cyl_mlp_forward(self.handle, features, **kw)
+
+    def grad(self, features, targets, **kw):
+        return steps_cyl_mlp_grad(self.handle, features, targets, **kw)
+
+    def train(self, train_in, steps, batch, **kw):
+        return steps_cyl_mlp_train(self.handle, train_in, steps, batch, **kw)
+
+    def save(self, path):
+        steps_cyl_mlp_save(self.handle, path)

@@ -31,6 +31,7 @@
 // straight into an FP32 total).
 #include "common.h"
 #include "pair_f64.h"
+#include "pair_fp32.h"
 
 namespace steps {
 
@@ -39,88 +40,14 @@ namespace {
 constexpr int kBlock = 256;  // targets per workgroup and sources per LDS tile
 constexpr int kSub = 32;     // sources per compensated flush
 
-struct alignas(16) SrcRec {
-    double x, y, z;
-    float m, h;
-};
-static_assert(sizeof(SrcRec) == 32, "source record must be 32 bytes");
-
 struct ExactArgs {
     const double *x, *y, *z, *m, *h;
     const int64_t *targets;  // null: target k is particle k
     float *ax, *ay, *az, *pot;
     double L, invL, halfL;
-    float Lf, L2f, m2Lf;  // L, L^2, -2L in FP32
-    int N, n_tgt, n_img;
+    ImageConsts c;
+    int N, n_tgt;
 };
-
-// The whole pair in FP64 with the spline law on every image; returns
-// S = sum F(r)/r, Fz = sum F(r)/r (d - nL) and P = -sum P(r).
-struct PairSums {
-    float S, Fz, P;
-};
-
-__device__ __noinline__ PairSums pair_general_f64(double dx, double dy, double d, double h, double L,
-                                                  int n_img) {
-    double s, fz, p;
-    pair_spline_f64(dx, dy, d, h, L, n_img, s, fz, p);
-    return PairSums{(float)s, (float)fz, (float)p};
-}
-
-__device__ __forceinline__ void kahan_add(float &sum, float &c, float x) {
-    const float y = x - c;
-    const float t = sum + y;
-    c = (t - sum) - y;
-    sum = t;
-}
-
-// NIMG >= 0: image count fixed at compile time; NIMG < 0: a.n_img at run time.
-template <int NIMG, bool POT>
-__device__ __forceinline__ void pair_fast(float dx, float dy, float d, const ExactArgs &a,
-                                          float &S, float &Fz, float &P) {
-    const int n_img = (NIMG >= 0) ? NIMG : a.n_img;
-    const float rho2 = __builtin_fmaf(dx, dx, dy * dy);
-    const float r2_0 = __builtin_fmaf(d, d, rho2);
-    const float ri0 = __builtin_amdgcn_rsqf(r2_0);
-    float Tp = 0.f, Tm = 0.f, Up = 0.f, Um = 0.f, Pp = 0.f, Pm = 0.f;
-    if (n_img >= 2) {
-        const float B = d * a.m2Lf;  // -2 L d
-#pragma unroll
-        for (int n = n_img; n >= 2; --n) {
-            const float nf = (float)n;
-            const float Cn = __builtin_fmaf(nf * nf, a.L2f, r2_0);
-            const float r2p = __builtin_fmaf(B, nf, Cn);   // image +n: dz = d - nL
-            const float r2m = __builtin_fmaf(B, -nf, Cn);  // image -n: dz = d + nL
-            const float rip = __builtin_amdgcn_rsqf(r2p);
-            const float rim = __builtin_amdgcn_rsqf(r2m);
-            Tp = __builtin_fmaf(rip * rip, rip, Tp);
-            Tm = __builtin_fmaf(rim * rim, rim, Tm);
-            Up += Tp;
-            Um += Tm;
-            if (POT) {
-                Pp += rip;
-                Pm += rim;
-            }
-        }
-    }
-    if (n_img >= 1) {
-        // n = +-1 directly: the shared-C form would lose ~3 bits here
-        const float dzp = d - a.Lf, dzm = d + a.Lf;
-        const float rip = __builtin_amdgcn_rsqf(__builtin_fmaf(dzp, dzp, rho2));
-        const float rim = __builtin_amdgcn_rsqf(__builtin_fmaf(dzm, dzm, rho2));
-        Tp = __builtin_fmaf(rip * rip, rip, Tp);
-        Tm = __builtin_fmaf(rim * rim, rim, Tm);
-        Up += Tp;
-        Um += Tm;
-        if (POT) {
-            Pp += rip;
-            Pm += rim;
-        }
-    }
-    S = __builtin_fmaf(ri0 * ri0, ri0, Tp + Tm);
-    Fz = __builtin_fmaf(d, S, -a.Lf * (Up - Um));
-    if (POT) P = ri0 + (Pp + Pm);
-}
 
 template <int NIMG, bool POT, bool COMP>
 __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
@@ -161,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
                 const float dx = (float)dx64, dy = (float)dy64, d = (float)d64;
                 const float hij = hi + src.h;
                 float S, Fz, P = 0.f;
-                pair_fast<NIMG, POT>(dx, dy, d, a, S, Fz, P);
+                pair_fast<NIMG, POT>(dx, dy, d, a.c, S, Fz, P);
                 const float r2_0 = __builtin_fmaf(d, d, __builtin_fmaf(dx, dx, dy * dy));
                 if (r2_0 < hij * hij || hij > (float)a.halfL) {
                     if ((int64_t)(base + s0 + s) == i) {
@@ -170,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
                         P = 0.f;
                     } else {
                         const PairSums g = pair_general_f64(dx64, dy64, d64, (double)hi + (double)src.h,
-                                                            a.L, (NIMG >= 0) ? NIMG : a.n_img);
+                                                            a.L, (NIMG >= 0) ? NIMG : a.c.n_img);
                         S = g.S;
                         Fz = g.Fz;
                         P = g.P;
@@ -218,7 +145,7 @@ hipError_t launch_t(const ExactArgs &a, hipStream_t stream) {
 
 template <bool POT, bool COMP>
 hipError_t launch_nimg(const ExactArgs &a, hipStream_t stream) {
-    switch (a.n_img) {
+    switch (a.c.n_img) {
         case 0: return launch_t<0, POT, COMP>(a, stream);
         case 1: return launch_t<1, POT, COMP>(a, stream);
         case 2: return launch_t<2, POT, COMP>(a, stream);
@@ -248,12 +175,12 @@ int launch_forces_exact(const double *pos, const double *mass, const double *eps
     a.L = L;
     a.invL = 1.0 / L;
     a.halfL = 0.5 * L;
-    a.Lf = (float)L;
-    a.L2f = (float)(L * L);
-    a.m2Lf = (float)(-2.0 * L);
+    a.c.Lf = (float)L;
+    a.c.L2f = (float)(L * L);
+    a.c.m2Lf = (float)(-2.0 * L);
+    a.c.n_img = n_img;
     a.N = (int)N;
     a.n_tgt = (int)n_tgt;
-    a.n_img = n_img;
     hipError_t e;
     const bool comp = (mode == STEPS_SUM_COMPENSATED);
     if (out_pot)

@@ -1,0 +1,170 @@
+// Device-side building blocks of the far-image correction network
+// (2 -> 64 -> 64 -> 64 -> 64 -> 2, SiLU): parameter layout, the packed
+// MFMA operand layout, and the per-wave forward pass over 32 samples.
+//
+// MFMA mapping (v_mfma_f32_32x32x16_bf16, FP32 accumulation).  Hidden
+// layers 2-4 are computed transposed, Y^T[64 x 32] = W[64 x 64] X^T[64 x 32],
+// with the 32 samples of a wave as the N dimension:
+//   A (32 x 16, weights):   lane l holds row l%32, k = 8(l/32) + e, e = 0..7
+//   B (16 x 32, inputs):    lane l holds column l%32, k = 8(l/32) + e
+//   D (32 x 32, outputs):   lane l holds column l%32, rows
+//                           8(v/4) + 4(l/32) + v%4 for v = 0..15
+// Each lane's D values of one layer are fed unchanged (after bias, SiLU and
+// BF16 rounding) as the B operand of the next layer: K step t takes the
+// values v = 8(t%2)..8(t%2)+7 of M block t/2.  K slot kappa = 16t + 8h + e
+// (h = l/32) therefore holds the physical feature
+//   phi(kappa) = 16t + 8(e/4) + 4h + e%4,
+// and the weight fragments are packed with their input columns permuted by
+// phi.  No data moves between lanes from layer to layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace steps {
+namespace mlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kWidth = 64;
+constexpr int kParams = 12802;
+// offsets in the flat parameter vector: W1 (64x2), b1, W2, b2, W3, b3, W4, b4,
+// W5 (2x64), b5; weights (fan_out, fan_in) row-major
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = 128;
+constexpr int OFF_W[3] = {192, 4352, 8512};   // W2, W3, W4
+constexpr int OFF_B[3] = {4288, 8448, 12608}; // b2, b3, b4
+constexpr int OFF_W5 = 12672;
+constexpr int OFF_B5 = 12800;
+
+// network domain and model constants (the learned correction, per unit L)
+constexpr float kRhoMin = 0.05f;
+constexpr float kRhoMax = 20.0f;
+constexpr float kOutScale = 0.02f;    // s(r) = 0.02 / (1 + r^2)
+constexpr double kRodInner = 1.5;     // rods from 1.5 L
+constexpr int kFarImages = 1024;      // ... to 1024.5 L
+
+// Packed inference parameters; copied to LDS by every kernel that evaluates
+// the network.
+struct alignas(16) Packed {
+    bf16x8 A[3][2][4][64];  // forward A fragments [layer][M block][K step][lane]
+    float W1[64][2];        // BF16-rounded, FP32 arithmetic
+    float b1[64];
+    float b[3][64];         // b2..b4
+    float W5[2][64];        // BF16-rounded
+    float b5[2];
+    float pad[2];
+};
+static_assert(sizeof(Packed) % 16 == 0, "packed parameters must be 16-byte sized");
+
+// Transposed fragments for the backward pass (A = W^T, K permuted by phi).
+struct alignas(16) PackedT {
+    bf16x8 AT[3][2][4][64];
+};
+
+__device__ __forceinline__ int phi(int kappa) {
+    const int t = kappa >> 4, h = (kappa >> 3) & 1, e = kappa & 7;
+    return 16 * t + 8 * (e >> 2) + 4 * h + (e & 3);
+}
+
+// physical output row of D element v of M block b for lane half h
+__device__ __forceinline__ int drow(int b, int v, int h) {
+    return 32 * b + 8 * (v >> 2) + 4 * h + (v & 3);
+}
+
+__device__ __forceinline__ float silu(float z) {
+    // z / (1 + e^-z) with the hardware exp2 and reciprocal
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
+    return z * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+__device__ __forceinline__ float silu_grad(float z) {
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
+    const float s = __builtin_amdgcn_rcpf(1.0f + e);
+    return s * __builtin_fmaf(z, 1.0f - s, 1.0f);
+}
+
+// Forward pass for the 32 samples of a wave.  Lanes l and l+32 both carry
+// the features (f1, f2) of sample l%32 and both return its outputs (o0, o1).
+// With CAPTURE, the pre-activations of layers 1..4 (zc, [4][64][32] FP32) and
+// the BF16 inputs of layers 2..4 (xc, [3][64][32]) are stored in
+// [feature][sample] layout (sample = column l%32) for the backward pass.
+template <bool CAPTURE>
+__device__ __forceinline__ void forward32(const Packed &P, float f1, float f2, float &o0, float &o1,
+                                          float *zc, __bf16 *xc) {
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5, col = lane & 31;
+    bf16x8 xb[4];
+    // layer 1 on the VALU: this lane computes the 32 units its K slots need
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int r = 16 * t + 8 * (e >> 2) + 4 * h + (e & 3);
+            const float z = __builtin_fmaf(P.W1[r][1], f2, __builtin_fmaf(P.W1[r][0], f1, P.b1[r]));
+            const float a = silu(z);
+            xb[t][e] = (__bf16)a;
+            if (CAPTURE) {
+                zc[r * 32 + col] = z;
+                xc[r * 32 + col] = xb[t][e];
+            }
+        }
+    }
+    float a4[2][16];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        f32x16 acc[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            acc[b] = (f32x16){0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                              0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(P.A[k][b][t][lane], xb[t], acc[b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = drow(b, v, h);
+                const float z = acc[b][v] + P.b[k][r];
+                const float a = silu(z);
+                if (CAPTURE) zc[(k + 1) * 64 * 32 + r * 32 + col] = z;
+                if (k < 2) {
+                    xb[2 * b + (v >> 3)][v & 7] = (__bf16)a;
+                    if (CAPTURE) xc[(k + 1) * 64 * 32 + r * 32 + col] = xb[2 * b + (v >> 3)][v & 7];
+                } else {
+                    a4[b][v] = a;
+                }
+            }
+        }
+    }
+    // layer 5 on the VALU: half-sums over this lane's 32 rows, then the halves
+    float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int r = drow(b, v, h);
+            p0 = __builtin_fmaf(P.W5[0][r], a4[b][v], p0);
+            p1 = __builtin_fmaf(P.W5[1][r], a4[b][v], p1);
+        }
+    }
+    const float q0 = __shfl_xor(p0, 32);
+    const float q1 = __shfl_xor(p1, 32);
+    // same operand order in both halves so they agree bitwise
+    o0 = (h ? (q0 + p0) : (p0 + q0)) + P.b5[0];
+    o1 = (h ? (q1 + p1) : (p1 + q1)) + P.b5[1];
+}
+
+// Copies the packed parameters into LDS cooperatively (16-byte chunks).
+__device__ __forceinline__ void load_packed(Packed *dst, const Packed *src) {
+    const int n = (int)(sizeof(Packed) / 16);
+    const uint4 *s = reinterpret_cast<const uint4 *>(src);
+    uint4 *d = reinterpret_cast<uint4 *>(dst);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+}
+
+}  // namespace mlp
+}  // namespace steps

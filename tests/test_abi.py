@@ -98,3 +98,87 @@ def test_binding_checks_tensor_arguments():
     with pytest.raises(ValueError, match="device"):
         sc.steps_cyl_forces(x, torch.zeros(4, dtype=torch.float64),
                             torch.zeros(4, dtype=torch.float64), 1.0, 8)
+
+
+# ---------------------------------------------------------------- network files
+def _write(path, blob):
+    with open(path, "wb") as f:
+        f.write(blob)
+
+
+def _valid_blob(params):
+    import struct
+
+    import numpy as np
+    p = np.asarray(params, dtype=np.float32)
+    body = p.tobytes()
+    h = 1469598103934665603
+    for b in body:
+        h ^= b
+        h = (h * 1099511628211) % (1 << 64)
+    return b"SCYLMLP1" + struct.pack("<II", 1, p.size) + body + struct.pack("<Q", h)
+
+
+@pytest.mark.parametrize("kind", ["missing", "magic", "version", "count", "truncated", "extra",
+                                  "checksum", "nan"])
+def test_mlp_load_rejects_bad_files(tmp_path, kind):
+    import numpy as np
+
+    import synth
+    p = synth.mlp_init(seed=1)
+    blob = _valid_blob(p)
+    path = tmp_path / "net.bin"
+    if kind == "magic":
+        blob = b"XCYLMLP1" + blob[8:]
+    elif kind == "version":
+        blob = blob[:8] + b"\x02\x00\x00\x00" + blob[12:]
+    elif kind == "count":
+        blob = blob[:12] + b"\x00\x00\x00\x00" + blob[16:]
+    elif kind == "truncated":
+        blob = blob[:-100]
+    elif kind == "extra":
+        blob = blob + b"\x00"
+    elif kind == "checksum":
+        blob = blob[:-8] + bytes([blob[-8] ^ 1]) + blob[-7:]
+    elif kind == "nan":
+        q = p.copy()
+        q[5] = np.nan
+        blob = _valid_blob(q)
+    if kind != "missing":
+        _write(path, blob)
+    h = ctypes.c_void_p()
+    rc = sc.lib().steps_cyl_mlp_load(os.fsencode(str(path)), ctypes.byref(h))
+    assert rc == sc.STEPS_EIO, sc.steps_cyl_last_error()
+    assert not h.value
+
+
+def test_mlp_load_accepts_a_valid_file_up_to_the_device(tmp_path):
+    import torch
+
+    import synth
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    path = tmp_path / "net.bin"
+    _write(path, _valid_blob(synth.mlp_init(seed=2)))
+    h = ctypes.c_void_p()
+    assert sc.lib().steps_cyl_mlp_load(os.fsencode(str(path)), ctypes.byref(h)) == sc.STEPS_ENODEV
+
+
+def test_mlp_create_rejects_bad_arguments():
+    import numpy as np
+    h = ctypes.c_void_p()
+    assert sc.lib().steps_cyl_mlp_create(None, ctypes.byref(h)) == sc.STEPS_EINVAL
+    p = np.zeros(sc.STEPS_MLP_PARAMS, dtype=np.float32)
+    p[17] = np.inf
+    assert sc.lib().steps_cyl_mlp_create(p.ctypes.data, ctypes.byref(h)) == sc.STEPS_EINVAL
+    assert sc.lib().steps_cyl_mlp_create(p.ctypes.data, None) == sc.STEPS_EINVAL
+
+
+def test_mlp_calls_reject_null_handles():
+    L = sc.lib()
+    assert L.steps_cyl_mlp_forward(None, P, P, 10, None) == sc.STEPS_EINVAL
+    assert L.steps_cyl_mlp_grad(None, P, P, 10, P, None, None) == sc.STEPS_EINVAL
+    assert L.steps_cyl_mlp_train(None, None, None) == sc.STEPS_EINVAL
+    assert L.steps_cyl_mlp_save(None, b"/tmp/x") == sc.STEPS_EINVAL
+    assert L.steps_cyl_mlp_samples(None, 4, P, P, None) == sc.STEPS_EINVAL
+    L.steps_cyl_mlp_destroy(None)
