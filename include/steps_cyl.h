@@ -106,7 +106,10 @@ int steps_cyl_forces_ex(const double *pos, const double *mass, const double *eps
 /*
  * steps_cyl_forces_f64 -- the same sum with every operation in FP64 on the
  * GPU (a slow reference for precision studies; same definitions, same
- * arguments as steps_cyl_forces_ex, FP64 outputs).
+ * arguments as steps_cyl_forces_ex, FP64 outputs).  Sources are split into
+ * chunks so that small target sets fill the GPU; the chunk partials live in
+ * stream-ordered scratch (hipMallocAsync, released on the stream), the one
+ * allocation this entry point makes.
  */
 int steps_cyl_forces_f64(const double *pos, const double *mass, const double *eps,
                          int64_t N, double L, int n_img,
@@ -205,6 +208,29 @@ int steps_cyl_mlp_save(const steps_cyl_mlp *net, const char *path);
  * for a missing, truncated, oversized or corrupt file (magic, version, count
  * or checksum), before any device allocation. */
 int steps_cyl_mlp_load(const char *path, steps_cyl_mlp **out);
+
+/*
+ * steps_cyl_forces_learned -- accelerations of all N particles with the
+ * exact images |n| <= 1 (spline-softened, as steps_cyl_forces with n_img = 1)
+ * plus the learned correction for the images 2 <= |n| <= 1024 (see above),
+ * i.e. an approximation of steps_cyl_forces with n_img = 1024.  Pairs with
+ * rho/L < 0.05 or rho/L > 20 (and no others) use the exact band instead of
+ * the network.  out_pot, when non-NULL, receives the potential of the images
+ * |n| <= 1 only (the network has no potential output).  Arguments as
+ * steps_cyl_forces; `net` is a handle from steps_cyl_mlp_create/_load.
+ * Softening of the replaced images is not modelled (they lie at least 1.5 L
+ * away; h_i + h_j below that is assumed).
+ */
+int steps_cyl_forces_learned(const double *pos, const double *mass, const double *eps,
+                             int64_t N, double L, const steps_cyl_mlp *net,
+                             float *out_acc, float *out_pot, hipStream_t stream);
+
+/* As steps_cyl_forces_learned for a target subset and summation mode
+ * (arguments as steps_cyl_forces_ex). */
+int steps_cyl_forces_learned_ex(const double *pos, const double *mass, const double *eps,
+                                int64_t N, double L, const steps_cyl_mlp *net,
+                                const int64_t *targets, int64_t n_targets, int mode,
+                                float *out_acc, float *out_pot, hipStream_t stream);
 
 /* Message for the last non-OK status returned to the calling thread
  * ("" if none).  The pointer stays valid until the thread's next call. */

@@ -19,7 +19,7 @@ __all__ = [
     "steps_cyl_mlp_create", "steps_cyl_mlp_destroy", "steps_cyl_mlp_get_params",
     "steps_cyl_mlp_set_params", "steps_cyl_mlp_forward", "steps_cyl_mlp_grad",
     "steps_cyl_mlp_samples", "steps_cyl_mlp_train", "steps_cyl_mlp_save", "steps_cyl_mlp_load",
-    "Mlp",
+    "Mlp", "steps_cyl_forces_learned", "steps_cyl_forces_learned_ex",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -80,6 +80,8 @@ _SIGNATURES = {
     "steps_cyl_mlp_train": [_VP, ctypes.POINTER(TrainCfg), _VP],
     "steps_cyl_mlp_save": [_VP, ctypes.c_char_p],
     "steps_cyl_mlp_load": [ctypes.c_char_p, _PP],
+    "steps_cyl_forces_learned": [_VP, _VP, _VP, _I64, _F64, _VP, _VP, _VP, _VP],
+    "steps_cyl_forces_learned_ex": [_VP, _VP, _VP, _I64, _F64, _VP, _VP, _I64, _I32, _VP, _VP, _VP],
 }
 
 
@@ -353,3 +355,41 @@ class Mlp:
 
     def save(self, path):
         steps_cyl_mlp_save(self.handle, path)
+
+
+def _handle(net):
+    return net.handle if isinstance(net, Mlp) else net
+
+
+def steps_cyl_forces_learned(pos, mass, eps, L, net, out_acc=None, out_pot=None, potential=True,
+                             stream=None):
+    """Learned-correction accelerations (3, N) FP32 and near-image
+    potentials (N,) FP32 of all particles; ``net`` an :class:`Mlp` or handle."""
+    import torch
+    N, p_pos, p_m, p_e = _sources(pos, mass, eps)
+    if out_acc is None:
+        out_acc = torch.empty((3, N), dtype=torch.float32, device=pos.device)
+    if potential and out_pot is None:
+        out_pot = torch.empty((N,), dtype=torch.float32, device=pos.device)
+    p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * N)
+    p_pot = _dev(out_pot, torch.float32, "out_pot", N) if potential else None
+    _check(lib().steps_cyl_forces_learned(p_pos, p_m, p_e, N, float(L), _handle(net), p_acc, p_pot,
+                                          _stream(stream, pos.device)))
+    return out_acc, (out_pot if potential else None)
+
+
+def steps_cyl_forces_learned_ex(pos, mass, eps, L, net, targets=None, mode=STEPS_SUM_COMPENSATED,
+                                out_acc=None, out_pot=None, potential=True, stream=None):
+    import torch
+    N, p_pos, p_m, p_e = _sources(pos, mass, eps)
+    T = N if targets is None else targets.numel()
+    p_t = None if targets is None else _dev(targets, torch.int64, "targets")
+    if out_acc is None:
+        out_acc = torch.empty((3, T), dtype=torch.float32, device=pos.device)
+    if potential and out_pot is None:
+        out_pot = torch.empty((T,), dtype=torch.float32, device=pos.device)
+    p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * T)
+    p_pot = _dev(out_pot, torch.float32, "out_pot", T) if potential else None
+    _check(lib().steps_cyl_forces_learned_ex(p_pos, p_m, p_e, N, float(L), _handle(net), p_t, T,
+                                             int(mode), p_acc, p_pot, _stream(stream, pos.device)))
+    return out_acc, (out_pot if potential else None)

@@ -10,6 +10,10 @@ int launch_forces_f64(const double *pos, const double *mass, const double *eps, 
                       double L, int n_img, const int64_t *targets, int64_t n_tgt, double *out_acc,
                       double *out_pot, hipStream_t stream);
 
+int launch_forces_learned(const double *pos, const double *mass, const double *eps, int64_t N, double L,
+                          const steps_cyl_mlp *net, const int64_t *targets, int64_t n_tgt, int mode,
+                          float *out_acc, float *out_pot, hipStream_t stream);
+
 namespace {
 
 int check_common(const void *pos, const void *mass, const void *eps, int64_t N, double L,
@@ -67,4 +71,31 @@ STEPS_API int steps_cyl_forces_f64(const double *pos, const double *mass, const 
     clear_error();
     return launch_forces_f64(pos, mass, eps, N, L, n_img, targets, n_targets, out_acc, out_pot,
                              stream);
+}
+
+STEPS_API int steps_cyl_forces_learned(const double *pos, const double *mass, const double *eps, int64_t N,
+                                       double L, const steps_cyl_mlp *net, float *out_acc, float *out_pot,
+                                       hipStream_t stream) {
+    int rc = check_common(pos, mass, eps, N, L, 1, nullptr, N, out_acc);
+    if (rc) return rc;
+    if (!net) return fail(STEPS_EINVAL, "net must be non-null");
+    if ((rc = require_device())) return rc;
+    clear_error();
+    return launch_forces_learned(pos, mass, eps, N, L, net, nullptr, N, STEPS_SUM_COMPENSATED, out_acc,
+                                 out_pot, stream);
+}
+
+STEPS_API int steps_cyl_forces_learned_ex(const double *pos, const double *mass, const double *eps,
+                                          int64_t N, double L, const steps_cyl_mlp *net,
+                                          const int64_t *targets, int64_t n_targets, int mode,
+                                          float *out_acc, float *out_pot, hipStream_t stream) {
+    int rc = check_common(pos, mass, eps, N, L, 1, targets, n_targets, out_acc);
+    if (rc) return rc;
+    if (!net) return fail(STEPS_EINVAL, "net must be non-null");
+    if (mode != STEPS_SUM_COMPENSATED && mode != STEPS_SUM_PLAIN)
+        return fail(STEPS_EINVAL, "mode=%d is not a summation mode", mode);
+    if ((rc = require_device())) return rc;
+    clear_error();
+    return launch_forces_learned(pos, mass, eps, N, L, net, targets, n_targets, mode, out_acc, out_pot,
+                                 stream);
 }

@@ -1,0 +1,241 @@
+// Learned far-image forces on gfx950: exact images |n| <= 1 plus the
+// network correction for the images 2 <= |n| <= 1024 (the paper adds its far
+// images through an interpolated correction table, Sect. 2.2, eq.
+// S1R2EwaldCorrectionTable; here a network of (|d|/L, rho/L) on BF16 MFMA
+// takes that role).
+//
+// Mapping.  A wave owns 32 targets, one per MFMA column; lanes l and l+32
+// share target l%32 and split each network layer between them.  A
+// workgroup of 4 waves (128 targets) walks the sources in LDS tiles of 256;
+// for every source the wave evaluates the 32 pairs (32 targets x 1 source)
+// as one network tile: layer 1 and the activations on the VALU, layers 2-4
+// as 8 MFMAs each, layer 5 on the VALU with a cross-half sum.  Pairs outside
+// the network's domain (rho/L < 0.05 or > 20) take the exact image band
+// instead; all 64 lanes share that sum (32 images each plus a butterfly
+// reduction), so a rare outside pair costs about 250 instructions instead
+// of a 2046-image serial loop in one lane.
+#include "common.h"
+#include "learned_model.h"
+#include "mlp_device.h"
+#include "pair_fp32.h"
+
+namespace steps {
+
+namespace {
+
+constexpr int kBlock = 256;     // 4 waves
+constexpr int kTargets = 128;   // targets per workgroup (32 per wave)
+constexpr int kTile = 256;      // sources per LDS tile
+constexpr int kSub = 32;        // sources per compensated flush
+
+struct LearnedArgs {
+    const double *x, *y, *z, *m, *h;
+    const int64_t *targets;
+    const mlp::Packed *P;
+    float *ax, *ay, *az, *pot;
+    double L, invL, halfL;
+    float invLf, invL2f;
+    ImageConsts c;  // n_img = 1
+    int N, n_tgt;
+};
+
+// Exact band 2 <= |n| <= 1024 for one pair (delta = d/L signed, r = rho/L),
+// shared by the 64 lanes of the wave; every lane returns the totals
+// (per unit G m / L^2).
+__device__ __forceinline__ void band_cooperative(float delta, float r, float &fz, float &fr) {
+    const int lane = threadIdx.x & 63;
+    const float r2 = r * r;
+    float sz = 0.f, sr = 0.f;
+#pragma unroll 4
+    for (int mm = 15; mm >= 0; --mm) {
+        const int q = 2 + lane + 64 * mm;
+        if (q <= mlp::kFarImages) {
+            const float qf = (float)q;
+            const float up = delta - qf, um = delta + qf;
+            const float ip = __builtin_amdgcn_rsqf(__builtin_fmaf(up, up, r2));
+            const float im = __builtin_amdgcn_rsqf(__builtin_fmaf(um, um, r2));
+            const float ip3 = ip * ip * ip, im3 = im * im * im;
+            sz = __builtin_fmaf(-up, ip3, __builtin_fmaf(-um, im3, sz));
+            sr = __builtin_fmaf(-r, ip3 + im3, sr);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        sz += __shfl_xor(sz, off);
+        sr += __shfl_xor(sr, off);
+    }
+    fz = sz;
+    fr = sr;
+}
+
+template <bool POT, bool COMP>
+__global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
+    __shared__ mlp::Packed P;
+    __shared__ SrcRec tile[kTile];
+    mlp::load_packed(&P, a.P);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 31, h = lane >> 5;
+    const int k = blockIdx.x * kTargets + wave * 32 + col;
+    const bool active = k < a.n_tgt;
+    const int64_t i = active ? (a.targets ? a.targets[k] : (int64_t)k) : 0;
+    const double xi = a.x[i], yi = a.y[i], zi = wrap_z(a.z[i], a.L);
+    const float hi = (float)a.h[i];
+
+    float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;
+    float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
+
+    for (int base = 0; base < a.N; base += kTile) {
+        __syncthreads();
+        const int j = base + tid;
+        if (j < a.N) {
+            SrcRec r;
+            r.x = a.x[j];
+            r.y = a.y[j];
+            r.z = wrap_z(a.z[j], a.L);
+            r.m = (float)a.m[j];
+            r.h = (float)a.h[j];
+            tile[tid] = r;
+        }
+        __syncthreads();
+        const int cnt = min(kTile, a.N - base);
+        for (int s0 = 0; s0 < cnt; s0 += kSub) {
+            const int e = min(kSub, cnt - s0);
+            float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f;
+            for (int s = 0; s < e; ++s) {
+                const SrcRec src = tile[s0 + s];
+                const bool self = (int64_t)(base + s0 + s) == i;
+                const double dx64 = xi - src.x, dy64 = yi - src.y;
+                const double d64 = min_image(zi - src.z, a.L, a.invL);
+                const float dx = (float)dx64, dy = (float)dy64, d = (float)d64;
+                const float hij = hi + src.h;
+                // near images |n| <= 1
+                float S, Fz, Pn = 0.f;
+                pair_fast<1, POT>(dx, dy, d, a.c, S, Fz, Pn);
+                const float rho2 = __builtin_fmaf(dx, dx, dy * dy);
+                const float r2_0 = __builtin_fmaf(d, d, rho2);
+                if (r2_0 < hij * hij || hij > (float)a.halfL) {
+                    if (self) {
+                        S = 0.f;
+                        Fz = 0.f;
+                        Pn = 0.f;
+                    } else {
+                        const PairSums g = pair_general_f64(dx64, dy64, d64, (double)hi + (double)src.h, a.L, 1);
+                        S = g.S;
+                        Fz = g.Fz;
+                        Pn = g.P;
+                    }
+                }
+                // far images 2 <= |n| <= 1024: network inside its domain
+                const float rho = __builtin_sqrtf(rho2);
+                const float r = rho * a.invLf;
+                const float delta = __builtin_fabsf(d) * a.invLf;
+                const bool inside = (r >= mlp::kRhoMin) && (r <= mlp::kRhoMax) && !self;
+                float f1, f2;
+                mlp::features_f32(delta, inside ? r : 1.0f, f1, f2);
+                float o0, o1;
+                mlp::forward32<false>(P, f1, f2, o0, o1, nullptr, nullptr);
+                float bz, br;
+                mlp::baseline_f32(delta, inside ? r : 1.0f, bz, br);
+                const float sc = mlp::out_scale_f32(r);
+                const float mz = __builtin_fmaf(sc, o0, bz);
+                float Rz = (d > 0.f) ? mz : ((d < 0.f) ? -mz : 0.f);
+                float Rr = __builtin_fmaf(sc, o1, br);
+                if (!inside) {
+                    Rz = 0.f;
+                    Rr = 0.f;
+                }
+                uint64_t outside = __ballot(!inside && !self && active && h == 0);
+                while (outside) {
+                    const int c = __builtin_ctzll(outside);
+                    outside &= outside - 1;
+                    const float dc = __shfl(d * a.invLf, c), rc = __shfl(r, c);
+                    float tz, tr;
+                    band_cooperative(dc, rc, tz, tr);
+                    if (col == c) {
+                        Rz = tz;
+                        Rr = tr;
+                    }
+                }
+                // a = -m_j [ S (dx, dy, *) - R_rho (dx, dy)/(rho L^2) , Fz - R_z / L^2 ]
+                const float rinv = rho > 0.f ? __builtin_amdgcn_rcpf(rho) : 0.f;
+                const float Seff = __builtin_fmaf(-Rr * a.invL2f, rinv, S);
+                const float Fzeff = __builtin_fmaf(-Rz, a.invL2f, Fz);
+                const float mS = src.m * Seff;
+                if (COMP) {
+                    px = __builtin_fmaf(mS, dx, px);
+                    py = __builtin_fmaf(mS, dy, py);
+                    pz = __builtin_fmaf(src.m, Fzeff, pz);
+                    if (POT) pp = __builtin_fmaf(src.m, Pn, pp);
+                } else {
+                    sx = __builtin_fmaf(mS, dx, sx);
+                    sy = __builtin_fmaf(mS, dy, sy);
+                    sz = __builtin_fmaf(src.m, Fzeff, sz);
+                    if (POT) sp = __builtin_fmaf(src.m, Pn, sp);
+                }
+            }
+            if (COMP) {
+                kahan_add(sx, cx, px);
+                kahan_add(sy, cy, py);
+                kahan_add(sz, cz, pz);
+                if (POT) kahan_add(sp, cp, pp);
+            }
+        }
+    }
+    if (active && h == 0) {
+        a.ax[k] = -(sx - cx);
+        a.ay[k] = -(sy - cy);
+        a.az[k] = -(sz - cz);
+        if (POT) a.pot[k] = -(sp - cp);
+    }
+}
+
+template <bool POT, bool COMP>
+hipError_t launch_t(const LearnedArgs &a, hipStream_t stream) {
+    const int grid = (a.n_tgt + kTargets - 1) / kTargets;
+    hipLaunchKernelGGL((forces_learned_kernel<POT, COMP>), dim3(grid), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+namespace mlp {
+const Packed *packed_of(const steps_cyl_mlp *net);
+}
+
+int launch_forces_learned(const double *pos, const double *mass, const double *eps, int64_t N, double L,
+                          const steps_cyl_mlp *net, const int64_t *targets, int64_t n_tgt, int mode,
+                          float *out_acc, float *out_pot, hipStream_t stream) {
+    LearnedArgs a;
+    a.x = pos;
+    a.y = pos + N;
+    a.z = pos + 2 * N;
+    a.m = mass;
+    a.h = eps;
+    a.targets = targets;
+    a.P = mlp::packed_of(net);
+    a.ax = out_acc;
+    a.ay = out_acc + n_tgt;
+    a.az = out_acc + 2 * n_tgt;
+    a.pot = out_pot;
+    a.L = L;
+    a.invL = 1.0 / L;
+    a.halfL = 0.5 * L;
+    a.invLf = (float)(1.0 / L);
+    a.invL2f = (float)(1.0 / (L * L));
+    a.c.Lf = (float)L;
+    a.c.L2f = (float)(L * L);
+    a.c.m2Lf = (float)(-2.0 * L);
+    a.c.n_img = 1;
+    a.N = (int)N;
+    a.n_tgt = (int)n_tgt;
+    const bool comp = (mode == STEPS_SUM_COMPENSATED);
+    hipError_t e;
+    if (out_pot)
+        e = comp ? launch_t<true, true>(a, stream) : launch_t<true, false>(a, stream);
+    else
+        e = comp ? launch_t<false, true>(a, stream) : launch_t<false, false>(a, stream);
+    return hip_status(e, "forces_learned launch");
+}
+
+}  // namespace steps

@@ -1,7 +1,9 @@
 // FP64 reference of the exact image sum on the GPU: every operation of the
 // pair sum in FP64 with the spline law on every image (same definitions as
-// the FP32 kernel).  A slow precision yardstick, one thread per target,
-// sources staged through LDS in tiles of 256.
+// the FP32 kernel).  A precision yardstick for sampled targets: the sources
+// are split into chunks over the grid's second dimension so that a few
+// thousand targets still fill the GPU, each (target block, chunk) writes
+// FP64 partial sums, and a second pass adds the chunks in order.
 #include "common.h"
 #include "pair_f64.h"
 
@@ -14,10 +16,38 @@ constexpr int kBlock = 256;
 struct RefArgs {
     const double *x, *y, *z, *m, *h;
     const int64_t *targets;
-    double *ax, *ay, *az, *pot;
+    double *part;  // [chunks][4][n_tgt]
     double L, invL;
-    int N, n_tgt, n_img;
+    int N, n_tgt, n_img, chunk;
 };
+
+// 1/sqrt(x) to FP64 precision: FP32 hardware estimate and two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y * (1.5 - 0.5 * x * y * y);
+}
+
+// All images of one pair; images farther than the softening length use
+// the Newtonian terms, the others the spline law.
+__device__ __forceinline__ void pair_f64(double dx, double dy, double d, double h, double L, int n_img,
+                                         double &s, double &fz, double &p) {
+    const double rho2 = dx * dx + dy * dy;
+    const double h2 = h * h;
+    if (rho2 >= h2) {
+        s = fz = p = 0.0;
+        for (int n = -n_img; n <= n_img; ++n) {
+            const double dz = d - (double)n * L;
+            const double ri = rsqrt_nr(rho2 + dz * dz);
+            const double ri3 = ri * ri * ri;
+            s += ri3;
+            fz += ri3 * dz;
+            p += ri;
+        }
+        return;
+    }
+    pair_spline_f64(dx, dy, d, h, L, n_img, s, fz, p);
+}
 
 __global__ __launch_bounds__(kBlock) void forces_f64_kernel(RefArgs a) {
     __shared__ double tx[kBlock], ty[kBlock], tz[kBlock], tm[kBlock], th[kBlock];
@@ -26,10 +56,11 @@ __global__ __launch_bounds__(kBlock) void forces_f64_kernel(RefArgs a) {
     const bool active = k < a.n_tgt;
     const int64_t i = active ? (a.targets ? a.targets[k] : (int64_t)k) : 0;
     const double xi = a.x[i], yi = a.y[i], zi = wrap_z(a.z[i], a.L), hi = a.h[i];
+    const int c0 = blockIdx.y * a.chunk, c1 = min(a.N, c0 + a.chunk);
     double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-    for (int base = 0; base < a.N; base += kBlock) {
+    for (int base = c0; base < c1; base += kBlock) {
         const int j = base + tid;
-        if (j < a.N) {
+        if (j < c1) {
             tx[tid] = a.x[j];
             ty[tid] = a.y[j];
             tz[tid] = wrap_z(a.z[j], a.L);
@@ -37,13 +68,13 @@ __global__ __launch_bounds__(kBlock) void forces_f64_kernel(RefArgs a) {
             th[tid] = a.h[j];
         }
         __syncthreads();
-        const int cnt = min(kBlock, a.N - base);
+        const int cnt = min(kBlock, c1 - base);
         for (int s = 0; s < cnt; ++s) {
             if ((int64_t)(base + s) == i) continue;
             const double dx = xi - tx[s], dy = yi - ty[s];
             const double d = min_image(zi - tz[s], a.L, a.invL);
             double S, Fz, P;
-            pair_spline_f64(dx, dy, d, hi + th[s], a.L, a.n_img, S, Fz, P);
+            pair_f64(dx, dy, d, hi + th[s], a.L, a.n_img, S, Fz, P);
             sx += tm[s] * S * dx;
             sy += tm[s] * S * dy;
             sz += tm[s] * Fz;
@@ -52,18 +83,31 @@ __global__ __launch_bounds__(kBlock) void forces_f64_kernel(RefArgs a) {
         __syncthreads();
     }
     if (active) {
-        a.ax[k] = -sx;
-        a.ay[k] = -sy;
-        a.az[k] = -sz;
-        if (a.pot) a.pot[k] = -sp;
+        double *q = a.part + (int64_t)blockIdx.y * 4 * a.n_tgt;
+        q[k] = sx;
+        q[a.n_tgt + k] = sy;
+        q[2 * a.n_tgt + k] = sz;
+        q[3 * a.n_tgt + k] = sp;
     }
+}
+
+__global__ void reduce_chunks_kernel(const double *part, int chunks, int n_tgt, double *acc, double *pot) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_tgt) return;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < chunks; ++c)
+        for (int q = 0; q < 4; ++q) v[q] += part[((int64_t)c * 4 + q) * n_tgt + k];
+    acc[k] = -v[0];
+    acc[n_tgt + k] = -v[1];
+    acc[2 * (int64_t)n_tgt + k] = -v[2];
+    if (pot) pot[k] = -v[3];
 }
 
 }  // namespace
 
-int launch_forces_f64(const double *pos, const double *mass, const double *eps, int64_t N,
-                      double L, int n_img, const int64_t *targets, int64_t n_tgt, double *out_acc,
-                      double *out_pot, hipStream_t stream) {
+int launch_forces_f64(const double *pos, const double *mass, const double *eps, int64_t N, double L,
+                      int n_img, const int64_t *targets, int64_t n_tgt, double *out_acc, double *out_pot,
+                      hipStream_t stream) {
     RefArgs a;
     a.x = pos;
     a.y = pos + N;
@@ -71,18 +115,30 @@ int launch_forces_f64(const double *pos, const double *mass, const double *eps, 
     a.m = mass;
     a.h = eps;
     a.targets = targets;
-    a.ax = out_acc;
-    a.ay = out_acc + n_tgt;
-    a.az = out_acc + 2 * n_tgt;
-    a.pot = out_pot;
     a.L = L;
     a.invL = 1.0 / L;
     a.N = (int)N;
     a.n_tgt = (int)n_tgt;
     a.n_img = n_img;
-    const int grid = (int)((n_tgt + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(forces_f64_kernel, dim3(grid), dim3(kBlock), 0, stream, a);
-    return hip_status(hipGetLastError(), "forces_f64 launch");
+    const int tblocks = (int)((n_tgt + kBlock - 1) / kBlock);
+    // enough (target block, chunk) pairs to fill the GPU, chunks of >= 256 sources
+    int chunks = (4096 + tblocks - 1) / tblocks;
+    const int max_chunks = (int)((N + kBlock - 1) / kBlock);
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks < 1) chunks = 1;
+    a.chunk = (int)(((N + chunks - 1) / chunks + kBlock - 1) / kBlock * kBlock);
+    chunks = (int)((N + a.chunk - 1) / a.chunk);
+    STEPS_CHECK_HIP(hipMallocAsync((void **)&a.part, sizeof(double) * 4 * (size_t)chunks * n_tgt, stream));
+    hipLaunchKernelGGL(forces_f64_kernel, dim3(tblocks, chunks), dim3(kBlock), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(reduce_chunks_kernel, dim3(tblocks), dim3(kBlock), 0, stream, a.part, chunks,
+                           (int)n_tgt, out_acc, out_pot);
+        e = hipGetLastError();
+    }
+    hipError_t f = hipFreeAsync(a.part, stream);
+    if (e != hipSuccess) return hip_status(e, "forces_f64 launch");
+    return hip_status(f, "forces_f64 scratch release");
 }
 
 }  // namespace steps
