@@ -232,6 +232,54 @@ int steps_cyl_forces_learned_ex(const double *pos, const double *mass, const dou
                                 const int64_t *targets, int64_t n_targets, int mode,
                                 float *out_acc, float *out_pot, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Time integration (Sect. 2.1, eq. ComovingEquationsOfMotionCylindrical and
+ * its kick-drift-kick integrator in cosmic time; Sect. 2.3 background).
+ *
+ * State: comoving positions x (pos, FP64 SoA) and momenta p = a^2 dx/dt
+ * (mom, FP64 SoA, [3][N]); with them the equations of motion read
+ *     dp/dt = (g(x) - F_h(x)) / a,   dx/dt = p / a^2,
+ * g the pair-sum acceleration of the force entry points (G = 1, a = 1) and
+ * F_h the radial field of the homogeneous cylinder (radius R_cyl, comoving
+ * density rho0, half-height Z = (n_img + 1/2) L, or 1024.5 L with a
+ * network) that the truncated image sum adds to every particle.  F_h is
+ * evaluated from the line-element integral over disk chords (the form that
+ * tends to -2 pi G rho0 rho as Z -> infinity; the paper's printed
+ * finite-height formula has the opposite sign and half of the logarithmic
+ * term).  Background: H(a)^2 = H0^2 (Or a^-4 + Om a^-3 + Ok a^-2 +
+ * OL a^{-3(1+w0+wa)} e^{3 wa (a-1)}) (CPL dark energy).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double a_begin, a_end;   /* scale factor at the start and the end of the step (> 0)   */
+    double H0;               /* Hubble constant in code units (G = 1), > 0                */
+    double Omega_m, Omega_L, Omega_r, Omega_k, w0, wa;  /* density parameters, CPL w(a)   */
+    double R_cyl, rho0;      /* compensated cylinder: radius and comoving density          */
+    int compensate;          /* 1: subtract F_h; 0: pair forces only                        */
+    int n_img;               /* exact images when net == NULL                               */
+    const steps_cyl_mlp *net;  /* learned correction, or NULL for the exact sum            */
+} steps_cyl_kdk_params;
+
+/* Kick and drift factors of one step (host only, no device work):
+ * out[0] = int dt/a over the first half, out[1] = int dt/a^2 over the
+ * whole step, out[2] = int dt/a over the second half, in cosmic time, with
+ * dt = t(a_end) - t(a_begin) (Gauss-Legendre in ln a) and the Friedmann
+ * equation advanced by fourth-order Runge-Kutta.  STEPS_EDOMAIN if H^2 is
+ * not positive over the step. */
+int steps_cyl_kdk_factors(const steps_cyl_kdk_params *params, double *out);
+
+/* F_h as a vector field at the particle positions: pos device [3][N] FP64,
+ * out device [3][N] FP64 (radial in x, y; zero along z), G = 1. */
+int steps_cyl_compensation(const double *pos, int64_t N, double R_cyl, double Z, double rho0,
+                           double *out, hipStream_t stream);
+
+/* One kick-drift-kick step from a_begin to a_end.  On entry acc_inout
+ * (device [3][N] FP32) must hold g at pos (from a force call or the previous
+ * step); on return pos, mom and acc_inout hold the new state.  z is wrapped
+ * into [0, L) in FP64.  One force evaluation per step. */
+int steps_cyl_kdk_step(double *pos, double *mom, const double *mass, const double *eps,
+                       int64_t N, double L, const steps_cyl_kdk_params *params,
+                       float *acc_inout, hipStream_t stream);
+
 /* Message for the last non-OK status returned to the calling thread
  * ("" if none).  The pointer stays valid until the thread's next call. */
 const char *steps_cyl_last_error(void);

@@ -20,6 +20,7 @@ __all__ = [
     "steps_cyl_mlp_set_params", "steps_cyl_mlp_forward", "steps_cyl_mlp_grad",
     "steps_cyl_mlp_samples", "steps_cyl_mlp_train", "steps_cyl_mlp_save", "steps_cyl_mlp_load",
     "Mlp", "steps_cyl_forces_learned", "steps_cyl_forces_learned_ex",
+    "KdkParams", "steps_cyl_kdk_factors", "steps_cyl_compensation", "steps_cyl_kdk_step",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -65,6 +66,17 @@ class TrainCfg(ctypes.Structure):
     ]
 
 
+class KdkParams(ctypes.Structure):
+    """Mirror of steps_cyl_kdk_params."""
+    _fields_ = [
+        ("a_begin", ctypes.c_double), ("a_end", ctypes.c_double), ("H0", ctypes.c_double),
+        ("Omega_m", ctypes.c_double), ("Omega_L", ctypes.c_double), ("Omega_r", ctypes.c_double),
+        ("Omega_k", ctypes.c_double), ("w0", ctypes.c_double), ("wa", ctypes.c_double),
+        ("R_cyl", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("compensate", ctypes.c_int), ("n_img", ctypes.c_int), ("net", ctypes.c_void_p),
+    ]
+
+
 _PP = ctypes.POINTER(ctypes.c_void_p)
 
 _SIGNATURES = {
@@ -82,6 +94,9 @@ _SIGNATURES = {
     "steps_cyl_mlp_load": [ctypes.c_char_p, _PP],
     "steps_cyl_forces_learned": [_VP, _VP, _VP, _I64, _F64, _VP, _VP, _VP, _VP],
     "steps_cyl_forces_learned_ex": [_VP, _VP, _VP, _I64, _F64, _VP, _VP, _I64, _I32, _VP, _VP, _VP],
+    "steps_cyl_kdk_factors": [ctypes.POINTER(KdkParams), _VP],
+    "steps_cyl_compensation": [_VP, _I64, _F64, _F64, _F64, _VP, _VP],
+    "steps_cyl_kdk_step": [_VP, _VP, _VP, _VP, _I64, _F64, ctypes.POINTER(KdkParams), _VP, _VP],
 }
 
 
@@ -393,3 +408,40 @@ def steps_cyl_forces_learned_ex(pos, mass, eps, L, net, targets=None, mode=STEPS
     _check(lib().steps_cyl_forces_learned_ex(p_pos, p_m, p_e, N, float(L), _handle(net), p_t, T,
                                              int(mode), p_acc, p_pot, _stream(stream, pos.device)))
     return out_acc, (out_pot if potential else None)
+
+
+# ---------------------------------------------------------------- time integration
+def kdk_params(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r=0.0, Omega_k=0.0, w0=-1.0, wa=0.0,
+               R_cyl=1.0, rho0=0.0, compensate=True, n_img=8, net=None):
+    return KdkParams(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r, Omega_k, w0, wa, R_cyl, rho0,
+                     1 if compensate else 0, int(n_img), _handle(net) if net is not None else None)
+
+
+def steps_cyl_kdk_factors(params):
+    """(K1, D, K2) of one step (host computation)."""
+    out = (ctypes.c_double * 3)()
+    _check(lib().steps_cyl_kdk_factors(ctypes.byref(params), ctypes.cast(out, ctypes.c_void_p)))
+    return tuple(out)
+
+
+def steps_cyl_compensation(pos, R_cyl, Z, rho0, out=None, stream=None):
+    import torch
+    N = pos.shape[1]
+    p = _dev(pos, torch.float64, "pos", 3 * N)
+    if out is None:
+        out = torch.empty((3, N), dtype=torch.float64, device=pos.device)
+    _check(lib().steps_cyl_compensation(p, N, float(R_cyl), float(Z), float(rho0),
+                                        _dev(out, torch.float64, "out", 3 * N),
+                                        _stream(stream, pos.device)))
+    return out
+
+
+def steps_cyl_kdk_step(pos, mom, mass, eps, L, params, acc, stream=None):
+    """One KDK step in place on device tensors pos, mom (3, N) FP64 and
+    acc (3, N) FP32 (pair acceleration at pos on entry and on return)."""
+    import torch
+    N, p_pos, p_m, p_e = _sources(pos, mass, eps)
+    p_mom = _dev(mom, torch.float64, "mom", 3 * N)
+    p_acc = _dev(acc, torch.float32, "acc", 3 * N)
+    _check(lib().steps_cyl_kdk_step(p_pos, p_mom, p_m, p_e, N, float(L), ctypes.byref(params),
+                                    p_acc, _stream(stream, pos.device)))

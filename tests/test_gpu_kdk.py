@@ -1,0 +1,143 @@
+"""GPU parity of the time integrator: the cylinder compensation against the
+FP64 oracle, one KDK step against the FP64 oracle step, time reversibility,
+and conservation of the axial momentum.
+
+Bars: F_h to 1e-10 relative (FP64 quadrature on both sides).  One step:
+the only FP32 input is the pair acceleration (relative error <= 1e-5), so
+momenta agree to 2e-5 of the largest kick and positions to D times that.
+Reversibility: a step forward and back returns to the start up to FP64
+round-off of the positions and FP32 re-evaluation of the same forces.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import background as bg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+LCDM = dict(H0=None, Om=0.3, OL=0.7)
+
+
+@pytest.fixture(scope="module")
+def sc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_20787_amd as m
+    return m
+
+
+def cosmo_for_load(L=1.0):
+    R = synth.r_max()
+    rho0 = 1.0 / (math.pi * R * R * L)
+    H0 = math.sqrt(8 * math.pi * rho0 / (3 * 0.3))
+    return bg.Cosmology(H0=H0, Om=0.3, OL=0.7), R, rho0
+
+
+def dev(a, dt=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda:0", dtype=dt)
+
+
+@pytest.mark.parametrize("Z", [1.5, 8.5, 1024.5])
+def test_compensation_matches_oracle(sc, Z):
+    R, rho0 = 3.157, 0.0319
+    rng = np.random.default_rng(int(Z))
+    rr = np.concatenate([rng.uniform(0, 1.3 * R, 60), [0.0, R, 1e-6, 2 * R]])
+    ph = rng.uniform(0, 2 * np.pi, rr.size)
+    pos = np.stack([rr * np.cos(ph), rr * np.sin(ph), rng.uniform(0, 1, rr.size)])
+    out = sc.steps_cyl_compensation(dev(pos), R, Z, rho0).cpu().numpy()
+    ref = bg.compensation(pos, R, Z, rho0)
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(out, ref, rtol=1e-10, atol=1e-12 * scale)
+
+
+def _state(sc, p):
+    pos = dev(p.pos)
+    m, e = dev(p.mass), dev(p.eps)
+    mom = torch.zeros_like(pos)
+    acc, _ = sc.steps_cyl_forces(pos, m, e, p.L, 8, potential=False)
+    return pos, mom, m, e, acc
+
+
+def test_one_step_matches_oracle(sc):
+    p = synth.displaced_load(1024, seed=2)
+    c, R, rho0 = cosmo_for_load()
+    pos, mom, m, e, acc = _state(sc, p)
+    # a non-zero initial momentum so the drift is exercised from the start
+    mom0 = 0.02 * np.random.default_rng(3).standard_normal((3, p.N))
+    mom.copy_(dev(mom0))
+    par = sc.kdk_params(0.05, 0.06, c.H0, c.Om, c.OL, R_cyl=R, rho0=rho0, n_img=8)
+    sc.steps_cyl_kdk_step(pos, mom, m, e, p.L, par, acc)
+    torch.cuda.synchronize()
+    x_ref, p_ref, a_ref = bg.kdk_step(p.pos, mom0, p.mass, p.eps, p.L, 8, 0.05, 0.06, c, R, rho0, 8.5)
+    K1, D, K2 = bg.kdk_factors(0.05, 0.06, c)
+    kick = (K1 + K2) * np.abs(a_ref).max()
+    assert np.abs(mom.cpu().numpy() - p_ref).max() <= 2e-5 * kick
+    dx = pos.cpu().numpy() - x_ref
+    dx[2] -= np.round(dx[2])
+    assert np.abs(dx).max() <= 2e-5 * kick * D + 1e-14
+    ea = np.linalg.norm(acc.double().cpu().numpy() - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)
+    assert ea.max() <= 1e-5
+
+
+def test_step_is_time_reversible(sc):
+    p = synth.displaced_load(2048, seed=4)
+    c, R, rho0 = cosmo_for_load()
+    pos, mom, m, e, acc = _state(sc, p)
+    x0, a0 = pos.clone(), acc.clone()
+    fw = sc.kdk_params(0.05, 0.06, c.H0, c.Om, c.OL, R_cyl=R, rho0=rho0, n_img=8)
+    bw = sc.kdk_params(0.06, 0.05, c.H0, c.Om, c.OL, R_cyl=R, rho0=rho0, n_img=8)
+    sc.steps_cyl_kdk_step(pos, mom, m, e, p.L, fw, acc)
+    pmax = float(mom.abs().max())
+    sc.steps_cyl_kdk_step(pos, mom, m, e, p.L, bw, acc)
+    torch.cuda.synchronize()
+    d = (pos - x0).cpu().numpy()
+    d[2] -= np.round(d[2])
+    assert np.abs(d).max() < 1e-12
+    assert float(mom.abs().max()) < 1e-7 * pmax
+    assert float((acc - a0).abs().max()) <= 1e-6 * float(a0.abs().max())
+
+
+def test_axial_momentum_is_conserved(sc):
+    p = synth.displaced_load(4096, seed=5)
+    c, R, rho0 = cosmo_for_load()
+    pos, mom, m, e, acc = _state(sc, p)
+    a_grid = np.exp(np.linspace(math.log(0.02), math.log(0.05), 9))
+    scale = 0.0
+    for a0, a1 in zip(a_grid[:-1], a_grid[1:]):
+        par = sc.kdk_params(a0, a1, c.H0, c.Om, c.OL, R_cyl=R, rho0=rho0, n_img=8)
+        sc.steps_cyl_kdk_step(pos, mom, m, e, p.L, par, acc)
+        scale = max(scale, float((m[None, :] * mom.abs()).sum(dim=1)[2]))
+    pz = float((m * mom[2]).sum())
+    print(f"P_z after 8 steps: {pz:.3e} (scale {scale:.3e})")
+    assert abs(pz) <= 1e-6 * scale
+
+
+def test_learned_steps_follow_exact_1024(sc):
+    import os
+    NET = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2602_20787_amd", "data", "correction_net.bin")
+    net = sc.Mlp.load(NET)
+    p = synth.displaced_load(4096, seed=6)
+    c, R, rho0 = cosmo_for_load()
+    runs = {}
+    for mode in ("learned", "exact"):
+        pos, mom, m, e, _ = _state(sc, p)
+        if mode == "learned":
+            acc, _ = sc.steps_cyl_forces_learned(pos, m, e, p.L, net, potential=False)
+        else:
+            acc, _ = sc.steps_cyl_forces(pos, m, e, p.L, 1024, potential=False)
+        a_grid = np.exp(np.linspace(math.log(0.02), math.log(0.03), 5))
+        for a0, a1 in zip(a_grid[:-1], a_grid[1:]):
+            par = sc.kdk_params(a0, a1, c.H0, c.Om, c.OL, R_cyl=R, rho0=rho0, n_img=1024,
+                                net=net if mode == "learned" else None)
+            sc.steps_cyl_kdk_step(pos, mom, m, e, p.L, par, acc)
+        torch.cuda.synchronize()
+        runs[mode] = mom.cpu().numpy()
+    d = np.linalg.norm(runs["learned"] - runs["exact"], axis=0) / np.linalg.norm(runs["exact"], axis=0)
+    print(f"learned vs exact-1024 momenta after 4 steps: max {d.max():.2e} median {np.median(d):.2e}")
+    assert d.max() <= 1e-4
+    net.close()
