@@ -20,6 +20,9 @@ FLAGS = [
     "-fvisibility=hidden",
     # packed FP32 VALU instructions stay off: ordinary float code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in VGPRs: no accumulator-register round trips before the
+    # VALU work on them
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
 
 

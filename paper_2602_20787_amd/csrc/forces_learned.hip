@@ -134,7 +134,14 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
                 float f1, f2;
                 mlp::features_f32(delta, inside ? r : 1.0f, f1, f2);
                 float o0, o1;
-                mlp::forward32<false>(P, f1, f2, o0, o1, nullptr, nullptr);
+                // Re-read the network from LDS on every source instead of
+                // pinning ~350 parameters per lane in registers: an opaque
+                // zero offset keeps the compiler from hoisting the loads.
+                int poff = 0;
+                asm volatile("" : "+v"(poff));
+                const mlp::Packed &Pl = *reinterpret_cast<const mlp::Packed *>(
+                    reinterpret_cast<const char *>(&P) + poff);
+                mlp::forward32<false>(Pl, f1, f2, o0, o1, nullptr, nullptr);
                 float bz, br;
                 mlp::baseline_f32(delta, inside ? r : 1.0f, bz, br);
                 const float sc = mlp::out_scale_f32(r);

@@ -37,41 +37,64 @@ namespace {
 // ---------------------------------------------------------------- packing
 // One thread per parameter: writes its BF16-rounded copies into the packed
 // forward and backward layouts.
+// lane half and position of feature r in the D layout: r = 32b + 8(v/4) + 4h + v%4
+__device__ __forceinline__ void dpos(int r, int &b, int &v, int &h) {
+    b = r >> 5;
+    const int rem = r & 31;
+    h = (rem >> 2) & 1;
+    v = 4 * (rem >> 3) + (rem & 3);
+}
+
+// K slot of feature i: i = phi(16t + 8h + e)
+__device__ __forceinline__ void kpos(int i, int &t, int &h, int &e) {
+    t = i >> 4;
+    const int rem = i & 15;
+    h = (rem >> 2) & 1;
+    e = 4 * (rem >> 3) + (rem & 3);
+}
+
 __device__ void pack_one(int p, float w, Packed *P, PackedT *PT) {
     if (p < OFF_B1) {
-        (&P->W1[0][0])[p] = (float)(__bf16)w;
+        const int r = p >> 1, c = p & 1;
+        int t, h, e;
+        kpos(r, t, h, e);
+        float *q = reinterpret_cast<float *>(&P->L1[h][8 * t + e]);
+        q[c] = (float)(__bf16)w;
     } else if (p < OFF_W[0]) {
-        P->b1[p - OFF_B1] = w;
+        const int r = p - OFF_B1;
+        int t, h, e;
+        kpos(r, t, h, e);
+        float *q = reinterpret_cast<float *>(&P->L1[h][8 * t + e]);
+        q[2] = w;
+        q[3] = 0.f;
     } else if (p < OFF_W5) {
         int k = 0;
         while (k < 2 && p >= OFF_W[k + 1]) ++k;
         const int q = p - OFF_W[k];
         if (q >= 4096) {  // bias of layer k+2
-            P->b[k][q - 4096] = w;
+            int b, v, h;
+            dpos(q - 4096, b, v, h);
+            P->Bias[h][k][b][v] = w;
             return;
         }
         const int o = q / 64, i = q % 64;  // W[o][i]
-        // forward fragment: row o of M block o/32, K slot kappa with phi(kappa) = i
-        {
-            const int b = o >> 5, row = o & 31;
-            // invert phi: i = 16t + 8(e/4) + 4h + e%4
-            const int t = i >> 4, rem = i & 15;
-            const int eh = rem >> 3, h = (rem >> 2) & 1, el = rem & 3;
-            const int e = 4 * eh + el;
-            const int lane = row + 32 * h;
-            reinterpret_cast<__bf16 *>(&P->A[k][b][t][lane])[e] = (__bf16)w;
+        {   // forward fragment: row o of M block o/32, K slot with phi = i
+            int t, h, e;
+            kpos(i, t, h, e);
+            const int lane = (o & 31) + 32 * h;
+            reinterpret_cast<__bf16 *>(&P->A[k][o >> 5][t][lane])[e] = (__bf16)w;
         }
-        // backward fragment of W^T: row i of M block i/32, K slot kappa with phi(kappa) = o
-        {
-            const int b = i >> 5, row = i & 31;
-            const int t = o >> 4, rem = o & 15;
-            const int eh = rem >> 3, h = (rem >> 2) & 1, el = rem & 3;
-            const int e = 4 * eh + el;
-            const int lane = row + 32 * h;
-            reinterpret_cast<__bf16 *>(&PT->AT[k][b][t][lane])[e] = (__bf16)w;
+        {   // backward fragment of W^T: row i of M block i/32, K slot with phi = o
+            int t, h, e;
+            kpos(o, t, h, e);
+            const int lane = (i & 31) + 32 * h;
+            reinterpret_cast<__bf16 *>(&PT->AT[k][i >> 5][t][lane])[e] = (__bf16)w;
         }
     } else if (p < OFF_B5) {
-        (&P->W5[0][0])[p - OFF_W5] = (float)(__bf16)w;
+        const int c = (p - OFF_W5) / 64, r = (p - OFF_W5) % 64;
+        int b, v, h;
+        dpos(r, b, v, h);
+        reinterpret_cast<float *>(&P->W5[h][b][v])[c] = (float)(__bf16)w;
     } else {
         P->b5[p - OFF_B5] = w;
     }
@@ -80,7 +103,7 @@ __device__ void pack_one(int p, float w, Packed *P, PackedT *PT) {
 __global__ void pack_kernel(const float *master, Packed *P, PackedT *PT) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < kParams) pack_one(p, master[p], P, PT);
-    if (p < 2) P->pad[p] = 0.f;
+    if (p < 2) P->b5[2 + p] = 0.f;
 }
 
 // ---------------------------------------------------------------- forward
@@ -223,7 +246,8 @@ __global__ __launch_bounds__(64) void train_kernel(TrainArgs A) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int r = drow(b, v, h);
-                const float da = __builtin_fmaf(P.W5[1][r], dd1, P.W5[0][r] * dd0);
+                const float2 w5 = P.W5[h][b][v];
+                const float da = __builtin_fmaf(w5.y, dd1, w5.x * dd0);
                 dz[b][v] = da * silu_grad(S.z[3][r][col]);
             }
     }

@@ -45,16 +45,21 @@ constexpr float kOutScale = 0.02f;    // s(r) = 0.02 / (1 + r^2)
 constexpr double kRodInner = 1.5;     // rods from 1.5 L
 constexpr int kFarImages = 1024;      // ... to 1024.5 L
 
-// Packed inference parameters; copied to LDS by every kernel that evaluates
-// the network.
+// Packed inference parameters, laid out so that every lane reads what it
+// needs as consecutive 16-byte chunks from one base address per lane half
+// h (the kernels copy this block to LDS):
+//   A     forward A fragments [layer][M block][K step][lane]
+//   L1    layer 1 row r = 16t + 8(e/4) + 4h + e%4 at [h][8t + e]:
+//         {W1[r][0], W1[r][1], b1[r], 0} (weights BF16-rounded)
+//   Bias  b_{k+2}[drow(b, v, h)] at [h][k][b][v]
+//   W5    {W5[0][r], W5[1][r]} for r = drow(b, v, h) at [h][b][v]
+//         (BF16-rounded)
 struct alignas(16) Packed {
-    bf16x8 A[3][2][4][64];  // forward A fragments [layer][M block][K step][lane]
-    float W1[64][2];        // BF16-rounded, FP32 arithmetic
-    float b1[64];
-    float b[3][64];         // b2..b4
-    float W5[2][64];        // BF16-rounded
-    float b5[2];
-    float pad[2];
+    bf16x8 A[3][2][4][64];
+    float4 L1[2][32];
+    alignas(16) float Bias[2][3][2][16];
+    float2 W5[2][2][16];
+    float b5[4];  // b5[0], b5[1], unused
 };
 static_assert(sizeof(Packed) % 16 == 0, "packed parameters must be 16-byte sized");
 
@@ -96,13 +101,17 @@ __device__ __forceinline__ void forward32(const Packed &P, float f1, float f2, f
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, col = lane & 31;
     bf16x8 xb[4];
+    const float4 *L1 = P.L1[h];
+    const float(*Bias)[2][16] = P.Bias[h];
+    const float2(*W5)[16] = P.W5[h];
     // layer 1 on the VALU: this lane computes the 32 units its K slots need
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int r = 16 * t + 8 * (e >> 2) + 4 * h + (e & 3);
-            const float z = __builtin_fmaf(P.W1[r][1], f2, __builtin_fmaf(P.W1[r][0], f1, P.b1[r]));
+            const float4 w = L1[8 * t + e];
+            const float z = __builtin_fmaf(w.y, f2, __builtin_fmaf(w.x, f1, w.z));
             const float a = silu(z);
             xb[t][e] = (__bf16)a;
             if (CAPTURE) {
@@ -117,8 +126,8 @@ __device__ __forceinline__ void forward32(const Packed &P, float f1, float f2, f
         f32x16 acc[2];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            acc[b] = (f32x16){0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                              0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            // the bias enters as the C operand of the first MFMA of the chain
+            acc[b] = *reinterpret_cast<const f32x16 *>(&Bias[k][b][0]);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(P.A[k][b][t][lane], xb[t], acc[b], 0, 0, 0);
@@ -128,7 +137,7 @@ __device__ __forceinline__ void forward32(const Packed &P, float f1, float f2, f
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int r = drow(b, v, h);
-                const float z = acc[b][v] + P.b[k][r];
+                const float z = acc[b][v];
                 const float a = silu(z);
                 if (CAPTURE) zc[(k + 1) * 64 * 32 + r * 32 + col] = z;
                 if (k < 2) {
@@ -146,9 +155,9 @@ __device__ __forceinline__ void forward32(const Packed &P, float f1, float f2, f
     for (int b = 0; b < 2; ++b) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int r = drow(b, v, h);
-            p0 = __builtin_fmaf(P.W5[0][r], a4[b][v], p0);
-            p1 = __builtin_fmaf(P.W5[1][r], a4[b][v], p1);
+            const float2 w = W5[b][v];
+            p0 = __builtin_fmaf(w.x, a4[b][v], p0);
+            p1 = __builtin_fmaf(w.y, a4[b][v], p1);
         }
     }
     const float q0 = __shfl_xor(p0, 32);
