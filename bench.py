@@ -1,8 +1,10 @@
-"""Benchmark of the exact S1 x R2 direct-sum force evaluation on one MI355X.
+"""Benchmark of the S1 x R2 direct-sum force evaluation on one MI355X.
 
 One step is one full force + potential evaluation (steps_cyl_forces) of
 N = 2^20 particles of the stereographic cylinder load (seed 0) with images
-|n| <= 8 along z: N^2 = 1.1e12 pair interactions.  Inputs are resident in HBM
+|n| <= 8 along z: N^2 = 1.1e12 pair interactions.  A second leg ("learned")
+compares the learned far-image correction with the exact |n| <= 1024 sum at
+--learned-n particles (time, speedup, accuracy against the FP64 reference).  Inputs are resident in HBM
 before the timed region; the timed region is bracketed by stream
 synchronisation and measured with HIP events on the stream the kernel runs on.
 
@@ -34,28 +36,14 @@ def flops_per_pair(n_img, potential=True):
     return (28 + 20 * n_img) if potential else (25 + 18 * n_img)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--N", type=int, default=1 << 20)
-    ap.add_argument("--n-img", type=int, default=8)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target duration of the oracle sample")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-
+def exact_leg(args, dev):
     import numpy as np
     import torch
 
     import synth
     import paper_2602_20787_amd as sc
-
-    dev = torch.device("cuda:0")
+    if args.exact_steps is not None:
+        args.steps = args.exact_steps
     N, n_img = args.N, args.n_img
     p = synth.cylinder_load(N, seed=0)
     pos = torch.from_numpy(p.pos).to(dev)
@@ -148,6 +136,143 @@ def main():
         out["rms_rel_err"] = float(f"{math.sqrt(np.mean(err ** 2)):.3e}")
         out["max_rel_pot_err"] = float(f"{perr.max():.3e}")
         out["err_sample_targets"] = k
+    return out
+
+
+def _chunks(n, parts):
+    step = (n + parts - 1) // parts
+    return [(a, min(n, a + step)) for a in range(0, n, step)]
+
+
+def learned_leg(args, dev):
+    """Learned correction vs exact |n| <= 1024 at N = args.learned_n: time of
+    a full evaluation of each (targets in chunks, so no launch runs longer
+    than ~2 minutes), speedup, and accuracy of both against the FP64 GPU
+    reference on 1024 targets."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2602_20787_amd as sc
+
+    N = args.learned_n
+    p = synth.cylinder_load(N, seed=0)
+    pos = torch.from_numpy(p.pos).to(dev)
+    m = torch.from_numpy(p.mass).to(dev)
+    e = torch.from_numpy(p.eps).to(dev)
+    net = sc.Mlp.load(os.path.join(ROOT, "paper_2602_20787_amd", "data", "correction_net.bin"))
+    stream = torch.cuda.current_stream(dev)
+    acc_l = torch.empty((3, N), dtype=torch.float32, device=dev)
+    acc_x = torch.empty((3, N), dtype=torch.float32, device=dev)
+    # chunk so that one exact |n| <= 1024 launch stays near a minute at most
+    parts = max(1, int(math.ceil(float(N) * N / 2.0e11)))
+    ranges = _chunks(N, parts)
+    idx = [torch.arange(a, b, dtype=torch.int64, device=dev) for a, b in ranges]
+
+    def run(kind):
+        total = 0.0
+        for (a, b), t in zip(ranges, idx):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            if kind == "learned":
+                o, _ = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=t,
+                                                      potential=False, stream=stream)
+                acc_l[:, a:b] = o
+            else:
+                o, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 1024, targets=t, potential=False,
+                                              stream=stream)
+                acc_x[:, a:b] = o
+            e1.record(stream)
+            torch.cuda.synchronize()
+            total += e0.elapsed_time(e1)
+            print(f"[bench] {kind} N={N} targets {a}..{b} done ({total / 1e3:.1f} s)",
+                  file=sys.stderr, flush=True)
+        return total
+
+    sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=idx[0][:1024], potential=False)
+    torch.cuda.synchronize()
+    ms_l = run("learned")
+    ms_x = run("exact")
+    t = torch.from_numpy(synth.target_sample(N, 1024, seed=7)).to(dev)
+    ref, _ = sc.steps_cyl_forces_f64(pos, m, e, p.L, 1024, targets=t, potential=False)
+    a8, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t, potential=False)
+    torch.cuda.synchronize()
+    r = ref.cpu().numpy()
+
+    def err(a):
+        a = a.double().cpu().numpy()
+        v = np.linalg.norm(a - r, axis=0) / np.linalg.norm(r, axis=0)
+        return float(f"{v.max():.3e}"), float(f"{np.median(v):.3e}")
+
+    el, ex, e8 = err(acc_l[:, t]), err(acc_x[:, t]), err(a8)
+    pairs = float(N) * N
+    net.close()
+    return {
+        "N": N, "workload": f"stereographic cylinder load N={N} (seed 0): exact |n|<=1 + "
+                            "network correction for 2<=|n|<=1024 vs exact |n|<=1024",
+        "ms_learned": round(ms_l, 1), "ms_exact1024": round(ms_x, 1),
+        "learned_G_pairs_per_s": round(pairs / (ms_l * 1e-3) / 1e9, 3),
+        "exact1024_G_pairs_per_s": round(pairs / (ms_x * 1e-3) / 1e9, 3),
+        "speedup_learned_vs_exact1024": round(ms_x / ms_l, 2),
+        "err_vs_f64_exact1024_targets": 1024,
+        "learned_max_rel_err": el[0], "learned_median_rel_err": el[1],
+        "exact1024_fp32_max_rel_err": ex[0], "exact8_max_rel_err": e8[0],
+    }
+
+
+def copy_leg(dev):
+    """A 256 MiB device-to-device copy, the yardstick for HBM byte counters."""
+    import torch
+    n = 256 << 20
+    src = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    return {"bytes_read": n, "bytes_written": n, "ms": round(ms, 4),
+            "GB_per_s": round(2 * n / (ms * 1e-3) / 1e9, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=1 << 20)
+    ap.add_argument("--n-img", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target duration of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned-n", type=int, default=1 << 17,
+                    help="particles of the learned-correction comparison (0 skips it)")
+    ap.add_argument("--exact-steps", type=int, default=None,
+                    help="timed exact evaluations (default --steps); 0 skips the exact leg")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a 256 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2602_20787_amd as sc
+
+    dev = torch.device("cuda:0")
+    out = exact_leg(args, dev) if (args.exact_steps is None or args.exact_steps > 0) else {
+        "metric": METRIC, "value": None, "unit": "G pair-interactions/s", "n_gpus": 1}
+    if args.learned_n:
+        out["learned"] = learned_leg(args, dev)
+    if args.copy_calib:
+        out["copy_calib"] = copy_leg(dev)
     print(json.dumps(out), flush=True)
 
 
