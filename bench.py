@@ -32,6 +32,24 @@ PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak (packed FMA
 PEAK_FP32_UNPACKED = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 
 
+# HBM bytes per launch of forces_exact_kernel<8,true,true> at N = 2^20 from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter
+# reads for a 256 MiB copy (profiles/forces_exact_N1M_nimg8_counters.md).
+# Valid only for the kernel sources they were measured on (hash below).
+TRAFFIC_EXACT_N1M = {"bytes": 5.398e9, "fetch_scale": 1.99971, "write_scale": 1.0,
+                     "sources_sha256_16": "6346884492484990"}
+TRAFFIC_SOURCES = ["forces_exact.hip", "pair_fp32.h", "pair_f64.h"]
+
+
+def exact_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2602_20787_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def flops_per_pair(n_img, potential=True):
     return (28 + 20 * n_img) if potential else (25 + 18 * n_img)
 
@@ -103,7 +121,11 @@ def exact_leg(args, dev):
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_VECTOR, 4),
-            "traffic": None,
+            "traffic": (TRAFFIC_EXACT_N1M["bytes"]
+                        if (N == 1 << 20 and n_img == 8
+                            and exact_sources_hash() == TRAFFIC_EXACT_N1M["sources_sha256_16"])
+                        else None),
+            "traffic_unit": "B per launch (HBM, counter-calibrated)",
             "flops_per_pair": flops_per_pair(n_img),
             "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_UNPACKED, 4),
             "kernel": "forces_exact_kernel<8,true,true>",
