@@ -123,8 +123,9 @@ int steps_cyl_forces_f64(const double *pos, const double *mass, const double *ep
  * the images 2 <= |n| <= 1024 of eq. ForceCylindrical are replaced by
  *     R_z   = sign(d) [ b_z(|d|, rho)   + s(rho) o_z ]
  *     R_rho =           b_rho(|d|, rho) + s(rho) o_rho       (per G m_j / L^2)
- * where (o_z, o_rho) is a network 2 -> 64 -> 64 -> 64 -> 64 -> 2 (SiLU after
- * every hidden layer) of the features f1 = 4|d|/L - 1 and
+ * where (o_z, o_rho) is a network 2 -> 64 -> 64 -> 64 -> 64 -> 2 (activation
+ * s(u) = u/(1 + 2^-u) = SiLU(u ln 2)/ln 2 after every hidden layer, i.e. SiLU
+ * with ln 2 absorbed into the weights) of the features f1 = 4|d|/L - 1 and
  * f2 = 2 ln(rho / (0.05 L)) / ln 400 - 1, s(rho) = 0.02 / (1 + (rho/L)^2),
  * and b is a fixed analytic baseline: the images on each side replaced by a
  * uniform rod from 1.5 L to 1024.5 L, plus the first midpoint-rule

@@ -23,9 +23,13 @@ where (o_z, o_rho) = MLP(f1, f2) and, with delta = |d|/L, r = rho/L:
     rod from 1.5 L to 1024.5 L (midpoint rule; closed form), plus the first
     midpoint-rule correction term (1/24) g'(1.5 L) at the inner rod ends,
     with g the field of one image as a function of its axial position.
-  * network: 2 -> 64 -> 64 -> 64 -> 64 -> 2, SiLU after every hidden layer,
-    linear output; parameters stored in the order of
-    ``synth.mlp_param_shapes`` (weights (fan_out, fan_in) row-major).
+  * network: 2 -> 64 -> 64 -> 64 -> 64 -> 2 with the activation
+    s(u) = u / (1 + 2^-u) after every hidden layer and a linear output;
+    s(u) = SiLU(u ln 2) / ln 2, so this is a SiLU network whose first-layer
+    weights and hidden biases carry a factor ln 2 and whose last-layer
+    weights carry 1 / ln 2 (exp2 then needs no pre-scaling on the GPU).
+    Parameters are stored in the order of ``synth.mlp_param_shapes``
+    (weights (fan_out, fan_in) row-major).
   * precision of the deployed network: weights rounded to BF16, activations
     entering layers 2-4 rounded to BF16 (round-to-nearest-even), everything
     else FP32 (``bf16=True`` reproduces those roundings; features and FP64
@@ -90,13 +94,17 @@ def bf16_round(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+LN2 = math.log(2.0)
+
+
 def silu(z):
-    return z / (1.0 + np.exp(-z))
+    """Activation s(u) = u / (1 + 2^-u)."""
+    return z / (1.0 + np.exp2(-z))
 
 
 def silu_grad(z):
-    s = 1.0 / (1.0 + np.exp(-z))
-    return s * (1.0 + z * (1.0 - s))
+    s = 1.0 / (1.0 + np.exp2(-z))
+    return s * (1.0 + z * LN2 * (1.0 - s))
 
 
 # ---------------------------------------------------------------- model parts

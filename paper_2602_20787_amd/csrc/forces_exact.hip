@@ -62,8 +62,10 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
     float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;  // totals
     float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;  // Kahan compensations
 
+    __shared__ float wave_hmax[kBlock / 64];
     for (int base = 0; base < a.N; base += kBlock) {
         const int j = base + tid;
+        float hj = 0.f;
         if (j < a.N) {
             SrcRec r;
             r.x = a.x[j];
@@ -71,9 +73,19 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
             r.z = wrap_z(a.z[j], a.L);
             r.m = (float)a.m[j];
             r.h = (float)a.h[j];
+            hj = r.h;
             tile[tid] = r;
         }
+        // largest softening in the tile: a per-target bound (h_i + max h_j)^2
+        // on r^2 below which a pair may need the spline
+        for (int off = 32; off >= 1; off >>= 1) hj = fmaxf(hj, __shfl_xor(hj, off));
+        if ((tid & 63) == 0) wave_hmax[tid >> 6] = hj;
         __syncthreads();
+        float hmax = wave_hmax[0];
+        for (int w = 1; w < kBlock / 64; ++w) hmax = fmaxf(hmax, wave_hmax[w]);
+        const float hb = hi + hmax;        // >= h_i + h_j for every source in the tile
+        const float thr2 = hb * hb;        // rounding is monotonic: >= (h_i + h_j)^2
+        const bool wide = hb > (float)a.halfL;
         const int cnt = min(kBlock, a.N - base);
         for (int s0 = 0; s0 < cnt; s0 += kSub) {
             const int e = min(kSub, cnt - s0);
@@ -86,11 +98,11 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
                 const double t = zi - src.z;
                 const double d64 = min_image(t, a.L, a.invL);
                 const float dx = (float)dx64, dy = (float)dy64, d = (float)d64;
-                const float hij = hi + src.h;
                 float S, Fz, P = 0.f;
                 pair_fast<NIMG, POT>(dx, dy, d, a.c, S, Fz, P);
                 const float r2_0 = __builtin_fmaf(d, d, __builtin_fmaf(dx, dx, dy * dy));
-                if (r2_0 < hij * hij || hij > (float)a.halfL) {
+                if ((wide || r2_0 < thr2) &&
+                    (r2_0 < (hi + src.h) * (hi + src.h) || hi + src.h > (float)a.halfL)) {
                     if ((int64_t)(base + s0 + s) == i) {
                         S = 0.f;
                         Fz = 0.f;

@@ -6,10 +6,14 @@
 //
 // Mapping.  A wave owns 32 targets, one per MFMA column; lanes l and l+32
 // share target l%32 and split each network layer between them.  A
-// workgroup of 4 waves (128 targets) walks the sources in LDS tiles of 256;
-// for every source the wave evaluates the 32 pairs (32 targets x 1 source)
-// as one network tile: layer 1 and the activations on the VALU, layers 2-4
-// as 8 MFMAs each, layer 5 on the VALU with a cross-half sum.  Pairs outside
+// workgroup of 4 waves (128 targets) walks the sources in LDS tiles of 256,
+// two sources per step: lane half 0 does the per-pair work (near images,
+// baseline, features, accumulation) for the even source and half 1 for the
+// odd one, and the wave then evaluates two network tiles of 32 pairs each
+// (32 targets x 1 source), the features crossing halves by one swap.  In a
+// tile, layer 1 and the activations run on the VALU, layers 2-4 as 8 MFMAs
+// each, layer 5 on the VALU with a cross-half sum.  Each half keeps its own
+// compensated sums; they are added at the end.  Pairs outside
 // the network's domain (rho/L < 0.05 or > 20) take the exact image band
 // instead; all 64 lanes share that sum (32 images each plus a butterfly
 // reduction), so a rare outside pair costs about 250 instructions instead
@@ -68,6 +72,52 @@ __device__ __forceinline__ void band_cooperative(float delta, float r, float &fz
     fr = sr;
 }
 
+// Per-pair work that does not involve the network: near images |n| <= 1,
+// the analytic baseline, features and the domain test.
+struct PairState {
+    float dx, dy, d, rho, r, S, Fz, Pn, f1, f2, bz, br, sc, m;
+    bool inside, band;  // band: outside the network domain, needs the exact band
+};
+
+template <bool POT>
+__device__ __forceinline__ PairState pair_state(const SrcRec &src, bool self, bool live, double xi,
+                                                double yi, double zi, float hi, const LearnedArgs &a) {
+    PairState q;
+    const double dx64 = xi - src.x, dy64 = yi - src.y;
+    const double d64 = min_image(zi - src.z, a.L, a.invL);
+    q.dx = (float)dx64;
+    q.dy = (float)dy64;
+    q.d = (float)d64;
+    q.m = live ? src.m : 0.f;
+    const float hij = hi + src.h;
+    q.Pn = 0.f;
+    pair_fast<1, POT>(q.dx, q.dy, q.d, a.c, q.S, q.Fz, q.Pn);
+    const float rho2 = __builtin_fmaf(q.dx, q.dx, q.dy * q.dy);
+    const float r2_0 = __builtin_fmaf(q.d, q.d, rho2);
+    if (r2_0 < hij * hij || hij > (float)a.halfL) {
+        if (self) {
+            q.S = 0.f;
+            q.Fz = 0.f;
+            q.Pn = 0.f;
+        } else {
+            const PairSums g = pair_general_f64(dx64, dy64, d64, (double)hi + (double)src.h, a.L, 1);
+            q.S = g.S;
+            q.Fz = g.Fz;
+            q.Pn = g.P;
+        }
+    }
+    q.rho = __builtin_sqrtf(rho2);
+    q.r = q.rho * a.invLf;
+    const float delta = __builtin_fabsf(q.d) * a.invLf;
+    q.inside = (q.r >= mlp::kRhoMin) && (q.r <= mlp::kRhoMax) && !self;
+    q.band = !q.inside && !self && live;
+    const float rr = q.inside ? q.r : 1.0f;
+    mlp::features_f32(delta, rr, q.f1, q.f2);
+    mlp::baseline_f32(delta, rr, q.bz, q.br);
+    q.sc = mlp::out_scale_f32(q.r);
+    return q;
+}
+
 template <bool POT, bool COMP>
 __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
     __shared__ mlp::Packed P;
@@ -82,6 +132,7 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
     const double xi = a.x[i], yi = a.y[i], zi = wrap_z(a.z[i], a.L);
     const float hi = (float)a.h[i];
 
+    // each lane half accumulates its own sources (h = 0: even, h = 1: odd)
     float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;
     float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
 
@@ -102,83 +153,61 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
         for (int s0 = 0; s0 < cnt; s0 += kSub) {
             const int e = min(kSub, cnt - s0);
             float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f;
-            for (int s = 0; s < e; ++s) {
-                const SrcRec src = tile[s0 + s];
-                const bool self = (int64_t)(base + s0 + s) == i;
-                const double dx64 = xi - src.x, dy64 = yi - src.y;
-                const double d64 = min_image(zi - src.z, a.L, a.invL);
-                const float dx = (float)dx64, dy = (float)dy64, d = (float)d64;
-                const float hij = hi + src.h;
-                // near images |n| <= 1
-                float S, Fz, Pn = 0.f;
-                pair_fast<1, POT>(dx, dy, d, a.c, S, Fz, Pn);
-                const float rho2 = __builtin_fmaf(dx, dx, dy * dy);
-                const float r2_0 = __builtin_fmaf(d, d, rho2);
-                if (r2_0 < hij * hij || hij > (float)a.halfL) {
-                    if (self) {
-                        S = 0.f;
-                        Fz = 0.f;
-                        Pn = 0.f;
-                    } else {
-                        const PairSums g = pair_general_f64(dx64, dy64, d64, (double)hi + (double)src.h, a.L, 1);
-                        S = g.S;
-                        Fz = g.Fz;
-                        Pn = g.P;
-                    }
-                }
-                // far images 2 <= |n| <= 1024: network inside its domain
-                const float rho = __builtin_sqrtf(rho2);
-                const float r = rho * a.invLf;
-                const float delta = __builtin_fabsf(d) * a.invLf;
-                const bool inside = (r >= mlp::kRhoMin) && (r <= mlp::kRhoMax) && !self;
-                float f1, f2;
-                mlp::features_f32(delta, inside ? r : 1.0f, f1, f2);
-                float o0, o1;
-                // Re-read the network from LDS on every source instead of
-                // pinning ~350 parameters per lane in registers: an opaque
-                // zero offset keeps the compiler from hoisting the loads.
+            for (int s = 0; s < e; s += 2) {
+                // this lane's source: s (h = 0) or s + 1 (h = 1); past the end the
+                // lane repeats source s with zero mass
+                const bool live = (s + h) < e;
+                const int js = live ? (s + h) : s;
+                const SrcRec src = tile[s0 + js];
+                const bool self = (int64_t)(base + s0 + js) == i;
+                PairState q = pair_state<POT>(src, self, live, xi, yi, zi, hi, a);
+                // network tiles: tile A holds the pairs of source s, tile B of s + 1;
+                // each half takes the other half's features by a cross-half swap
+                const float g1 = __shfl_xor(q.f1, 32), g2 = __shfl_xor(q.f2, 32);
+                const float fa1 = h ? g1 : q.f1, fa2 = h ? g2 : q.f2;
+                const float fb1 = h ? q.f1 : g1, fb2 = h ? q.f2 : g2;
                 int poff = 0;
                 asm volatile("" : "+v"(poff));
                 const mlp::Packed &Pl = *reinterpret_cast<const mlp::Packed *>(
                     reinterpret_cast<const char *>(&P) + poff);
-                mlp::forward32<false>(Pl, f1, f2, o0, o1, nullptr, nullptr);
-                float bz, br;
-                mlp::baseline_f32(delta, inside ? r : 1.0f, bz, br);
-                const float sc = mlp::out_scale_f32(r);
-                const float mz = __builtin_fmaf(sc, o0, bz);
-                float Rz = (d > 0.f) ? mz : ((d < 0.f) ? -mz : 0.f);
-                float Rr = __builtin_fmaf(sc, o1, br);
-                if (!inside) {
+                float oa0, oa1, ob0, ob1;
+                mlp::forward32<false>(Pl, fa1, fa2, oa0, oa1, nullptr, nullptr);
+                mlp::forward32<false>(Pl, fb1, fb2, ob0, ob1, nullptr, nullptr);
+                const float o0 = h ? ob0 : oa0, o1 = h ? ob1 : oa1;
+                const float mz = __builtin_fmaf(q.sc, o0, q.bz);
+                float Rz = (q.d > 0.f) ? mz : ((q.d < 0.f) ? -mz : 0.f);
+                float Rr = __builtin_fmaf(q.sc, o1, q.br);
+                if (!q.inside) {
                     Rz = 0.f;
                     Rr = 0.f;
                 }
-                uint64_t outside = __ballot(!inside && !self && active && h == 0);
+                uint64_t outside = __ballot(q.band && active);
                 while (outside) {
                     const int c = __builtin_ctzll(outside);
                     outside &= outside - 1;
-                    const float dc = __shfl(d * a.invLf, c), rc = __shfl(r, c);
+                    const float dc = __shfl(q.d * a.invLf, c), rc = __shfl(q.r, c);
                     float tz, tr;
                     band_cooperative(dc, rc, tz, tr);
-                    if (col == c) {
+                    if (lane == c) {
                         Rz = tz;
                         Rr = tr;
                     }
                 }
                 // a = -m_j [ S (dx, dy, *) - R_rho (dx, dy)/(rho L^2) , Fz - R_z / L^2 ]
-                const float rinv = rho > 0.f ? __builtin_amdgcn_rcpf(rho) : 0.f;
-                const float Seff = __builtin_fmaf(-Rr * a.invL2f, rinv, S);
-                const float Fzeff = __builtin_fmaf(-Rz, a.invL2f, Fz);
-                const float mS = src.m * Seff;
+                const float rinv = q.rho > 0.f ? __builtin_amdgcn_rcpf(q.rho) : 0.f;
+                const float Seff = __builtin_fmaf(-Rr * a.invL2f, rinv, q.S);
+                const float Fzeff = __builtin_fmaf(-Rz, a.invL2f, q.Fz);
+                const float mS = q.m * Seff;
                 if (COMP) {
-                    px = __builtin_fmaf(mS, dx, px);
-                    py = __builtin_fmaf(mS, dy, py);
-                    pz = __builtin_fmaf(src.m, Fzeff, pz);
-                    if (POT) pp = __builtin_fmaf(src.m, Pn, pp);
+                    px = __builtin_fmaf(mS, q.dx, px);
+                    py = __builtin_fmaf(mS, q.dy, py);
+                    pz = __builtin_fmaf(q.m, Fzeff, pz);
+                    if (POT) pp = __builtin_fmaf(q.m, q.Pn, pp);
                 } else {
-                    sx = __builtin_fmaf(mS, dx, sx);
-                    sy = __builtin_fmaf(mS, dy, sy);
-                    sz = __builtin_fmaf(src.m, Fzeff, sz);
-                    if (POT) sp = __builtin_fmaf(src.m, Pn, sp);
+                    sx = __builtin_fmaf(mS, q.dx, sx);
+                    sy = __builtin_fmaf(mS, q.dy, sy);
+                    sz = __builtin_fmaf(q.m, Fzeff, sz);
+                    if (POT) sp = __builtin_fmaf(q.m, q.Pn, sp);
                 }
             }
             if (COMP) {
@@ -189,11 +218,14 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
             }
         }
     }
+    // combine the halves: value and compensation of the odd sources join the even ones
+    const float ox = __shfl_xor(sx - cx, 32), oy = __shfl_xor(sy - cy, 32);
+    const float oz = __shfl_xor(sz - cz, 32), op = __shfl_xor(sp - cp, 32);
     if (active && h == 0) {
-        a.ax[k] = -(sx - cx);
-        a.ay[k] = -(sy - cy);
-        a.az[k] = -(sz - cz);
-        if (POT) a.pot[k] = -(sp - cp);
+        a.ax[k] = -((sx - cx) + ox);
+        a.ay[k] = -((sy - cy) + oy);
+        a.az[k] = -((sz - cz) + oz);
+        if (POT) a.pot[k] = -((sp - cp) + op);
     }
 }
 

@@ -1,5 +1,5 @@
 // Device-side building blocks of the far-image correction network
-// (2 -> 64 -> 64 -> 64 -> 64 -> 2, SiLU): parameter layout, the packed
+// (2 -> 64 -> 64 -> 64 -> 64 -> 2, base-2 SiLU): parameter layout, the packed
 // MFMA operand layout, and the per-wave forward pass over 32 samples.
 //
 // MFMA mapping (v_mfma_f32_32x32x16_bf16, FP32 accumulation).  Hidden
@@ -78,16 +78,17 @@ __device__ __forceinline__ int drow(int b, int v, int h) {
     return 32 * b + 8 * (v >> 2) + 4 * h + (v & 3);
 }
 
-__device__ __forceinline__ float silu(float z) {
-    // z / (1 + e^-z) with the hardware exp2 and reciprocal
-    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
-    return z * __builtin_amdgcn_rcpf(1.0f + e);
+// Activation s(u) = u / (1 + 2^-u) = SiLU(u ln 2) / ln 2: SiLU with the
+// factor ln 2 absorbed into the adjacent weights, so that the hardware exp2
+// needs no scaling (two VALU operations and two transcendentals per unit).
+__device__ __forceinline__ float silu(float u) {
+    return u * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-u));
 }
 
-__device__ __forceinline__ float silu_grad(float z) {
-    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
-    const float s = __builtin_amdgcn_rcpf(1.0f + e);
-    return s * __builtin_fmaf(z, 1.0f - s, 1.0f);
+// ds/du = sigma (1 + u ln2 (1 - sigma)), sigma = 1 / (1 + 2^-u)
+__device__ __forceinline__ float silu_grad(float u) {
+    const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-u));
+    return sg * __builtin_fmaf(u * 0.6931471805599453f, 1.0f - sg, 1.0f);
 }
 
 // Forward pass for the 32 samples of a wave.  Lanes l and l+32 both carry

@@ -29,6 +29,13 @@ def test_bf16_round_is_round_to_nearest_even():
     np.testing.assert_array_equal(mlp.bf16_round(x), ref)
 
 
+class _Silu2(torch.nn.Module):
+    """SiLU(u ln 2) / ln 2 from the library SiLU."""
+
+    def forward(self, u):
+        return torch.nn.functional.silu(u * math.log(2.0)) / math.log(2.0)
+
+
 def _torch_net(params):
     layers = mlp.unpack(params)
     mods = []
@@ -38,8 +45,17 @@ def _torch_net(params):
         lin.bias.data = torch.from_numpy(b)
         mods.append(lin)
         if k < len(layers) - 1:
-            mods.append(torch.nn.SiLU())
+            mods.append(_Silu2())
     return torch.nn.Sequential(*mods)
+
+
+def test_activation_is_rescaled_silu():
+    u = np.linspace(-30, 30, 601)
+    ref = torch.nn.functional.silu(torch.from_numpy(u) * math.log(2.0)).numpy() / math.log(2.0)
+    np.testing.assert_allclose(mlp.silu(u), ref, rtol=1e-14, atol=1e-300)
+    h = 1e-6
+    fd = (mlp.silu(u + h) - mlp.silu(u - h)) / (2 * h)
+    np.testing.assert_allclose(mlp.silu_grad(u), fd, rtol=1e-7, atol=1e-9)
 
 
 def test_forward_matches_library_network():
