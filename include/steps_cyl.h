@@ -234,6 +234,40 @@ int steps_cyl_forces_learned_ex(const double *pos, const double *mass, const dou
                                 float *out_acc, float *out_pot, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Tabulated far-image correction (Sect. 2.2, eq. S1R2EwaldCorrectionTable:
+ * a correction tabulated on an equally spaced grid in the cylindrical
+ * coordinates, interpolated with CIC or TSC and added to the nearest-image
+ * forces).  The table holds the image band 2 <= |n| <= n_far of one unit
+ * mass, T = (T_z, T_rho) per G m / L^2, at delta = |d|/L = i/(2 n_delta)
+ * (i = -1..n_delta+1) and r = rho/L = j rho_max/n_rho (j = -1..n_rho+1),
+ * computed in FP64 and stored in FP32; R_z = sign(d) T_z, R_rho = T_rho.
+ * Pairs with rho/L > rho_max use the exact band.  The table is in units of
+ * L, so one table serves every period.
+ * ---------------------------------------------------------------------- */
+typedef struct steps_cyl_table steps_cyl_table;   /* opaque; owns device memory */
+
+/* Builds a table (device memory owned by the handle; synchronises stream).
+ * 2 <= n_delta, n_rho <= 4096; 0 < rho_max <= 1e4; 2 <= n_far <= 2^20. */
+int steps_cyl_table_create(int n_delta, int n_rho, double rho_max, int n_far,
+                           hipStream_t stream, steps_cyl_table **out);
+
+/* Releases a table (NULL is ignored). */
+void steps_cyl_table_destroy(steps_cyl_table *table);
+
+/* Copies the nodes to host_out[(n_rho+3) * (n_delta+3) * 2] FP32, node
+ * (i, j) at ((j+1) * (n_delta+3) + i+1) * 2 as (T_z, T_rho) (synchronous). */
+int steps_cyl_table_values(const steps_cyl_table *table, float *host_out);
+
+/* Accelerations with the exact images |n| <= 1 (spline-softened) plus the
+ * interpolated band (order 1 = CIC, 2 = TSC); out_pot, when non-NULL, gets
+ * the |n| <= 1 potential.  Other arguments as steps_cyl_forces_ex
+ * (compensated summation). */
+int steps_cyl_forces_table(const double *pos, const double *mass, const double *eps,
+                           int64_t N, double L, const steps_cyl_table *table, int order,
+                           const int64_t *targets, int64_t n_targets,
+                           float *out_acc, float *out_pot, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Time integration (Sect. 2.1, eq. ComovingEquationsOfMotionCylindrical and
  * its kick-drift-kick integrator in cosmic time; Sect. 2.3 background).
  *

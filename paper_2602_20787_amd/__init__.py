@@ -21,6 +21,8 @@ __all__ = [
     "steps_cyl_mlp_samples", "steps_cyl_mlp_train", "steps_cyl_mlp_save", "steps_cyl_mlp_load",
     "Mlp", "steps_cyl_forces_learned", "steps_cyl_forces_learned_ex",
     "KdkParams", "steps_cyl_kdk_factors", "steps_cyl_compensation", "steps_cyl_kdk_step",
+    "CorrectionTable", "steps_cyl_table_create", "steps_cyl_table_destroy",
+    "steps_cyl_table_values", "steps_cyl_forces_table",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -97,6 +99,9 @@ _SIGNATURES = {
     "steps_cyl_kdk_factors": [ctypes.POINTER(KdkParams), _VP],
     "steps_cyl_compensation": [_VP, _I64, _F64, _F64, _F64, _VP, _VP],
     "steps_cyl_kdk_step": [_VP, _VP, _VP, _VP, _I64, _F64, ctypes.POINTER(KdkParams), _VP, _VP],
+    "steps_cyl_table_create": [_I32, _I32, _F64, _I32, _VP, _PP],
+    "steps_cyl_table_values": [_VP, _VP],
+    "steps_cyl_forces_table": [_VP, _VP, _VP, _I64, _F64, _VP, _I32, _VP, _I64, _VP, _VP, _VP],
 }
 
 
@@ -114,6 +119,8 @@ def lib():
             f.restype = ctypes.c_int
         L.steps_cyl_mlp_destroy.argtypes = [_VP]
         L.steps_cyl_mlp_destroy.restype = None
+        L.steps_cyl_table_destroy.argtypes = [_VP]
+        L.steps_cyl_table_destroy.restype = None
         L.steps_cyl_last_error.restype = ctypes.c_char_p
         L.steps_cyl_last_error.argtypes = []
         L.steps_cyl_version.restype = ctypes.c_char_p
@@ -445,3 +452,65 @@ def steps_cyl_kdk_step(pos, mom, mass, eps, L, params, acc, stream=None):
     p_acc = _dev(acc, torch.float32, "acc", 3 * N)
     _check(lib().steps_cyl_kdk_step(p_pos, p_mom, p_m, p_e, N, float(L), ctypes.byref(params),
                                     p_acc, _stream(stream, pos.device)))
+
+
+# ---------------------------------------------------------------- correction table
+def steps_cyl_table_create(n_delta=128, n_rho=144, rho_max=6.4, n_far=1024, stream=None):
+    import torch
+    h = ctypes.c_void_p()
+    _check(lib().steps_cyl_table_create(int(n_delta), int(n_rho), float(rho_max), int(n_far),
+                                        _stream(stream, torch.device("cuda:0")), ctypes.byref(h)))
+    return h.value
+
+
+def steps_cyl_table_destroy(handle):
+    if handle:
+        lib().steps_cyl_table_destroy(handle)
+
+
+def steps_cyl_table_values(handle, n_delta, n_rho):
+    """Nodes as an FP32 array (n_rho + 3, n_delta + 3, 2)."""
+    import numpy as np
+    out = np.empty((n_rho + 3, n_delta + 3, 2), dtype=np.float32)
+    _check(lib().steps_cyl_table_values(handle, out.ctypes.data))
+    return out
+
+
+class CorrectionTable:
+    """Owning wrapper of a table handle."""
+
+    def __init__(self, n_delta=128, n_rho=144, rho_max=6.4, n_far=1024):
+        self.n_delta, self.n_rho, self.rho_max, self.n_far = n_delta, n_rho, rho_max, n_far
+        self.handle = steps_cyl_table_create(n_delta, n_rho, rho_max, n_far)
+
+    def close(self):
+        if self.handle:
+            steps_cyl_table_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def values(self):
+        return steps_cyl_table_values(self.handle, self.n_delta, self.n_rho)
+
+
+def steps_cyl_forces_table(pos, mass, eps, L, table, order=2, targets=None, out_acc=None,
+                           out_pot=None, potential=True, stream=None):
+    import torch
+    N, p_pos, p_m, p_e = _sources(pos, mass, eps)
+    T = N if targets is None else targets.numel()
+    p_t = None if targets is None else _dev(targets, torch.int64, "targets")
+    if out_acc is None:
+        out_acc = torch.empty((3, T), dtype=torch.float32, device=pos.device)
+    if potential and out_pot is None:
+        out_pot = torch.empty((T,), dtype=torch.float32, device=pos.device)
+    p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * T)
+    p_pot = _dev(out_pot, torch.float32, "out_pot", T) if potential else None
+    h = table.handle if isinstance(table, CorrectionTable) else table
+    _check(lib().steps_cyl_forces_table(p_pos, p_m, p_e, N, float(L), h, int(order), p_t, T,
+                                        p_acc, p_pot, _stream(stream, pos.device)))
+    return out_acc, (out_pot if potential else None)

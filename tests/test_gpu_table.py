@@ -1,0 +1,82 @@
+"""GPU parity of the tabulated far-image correction against its FP64
+oracle, and its accuracy against the exact |n| <= 1024 sum.
+
+Bars: nodes to FP32 rounding (2e-7 relative or 1e-9 absolute); forces of
+the tabulated scheme to 2e-5 relative (FP32 near terms and FP32 weights over
+FP32 nodes, as in the learned scheme).  Accuracy against |n| <= 1024 is
+reported with the paper's 144 x 128 grid; the bar is the interpolation
+error of that grid (h^2 f''/8 ~ 1e-3 of the band), not 1e-5.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import table as ot
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_20787_amd as m
+    return m
+
+
+def to_dev(p):
+    d = torch.device("cuda:0")
+    return (torch.from_numpy(p.pos).to(d), torch.from_numpy(p.mass).to(d),
+            torch.from_numpy(p.eps).to(d))
+
+
+def rel(a, ref):
+    a = a.detach().double().cpu().numpy()
+    r = ref.detach().double().cpu().numpy() if hasattr(ref, "detach") else ref
+    return np.linalg.norm(a - r, axis=0) / np.linalg.norm(r, axis=0)
+
+
+def test_table_nodes_match_oracle(sc):
+    t = sc.CorrectionTable(32, 40, 5.0, 1024)
+    v = t.values().astype(np.float64)
+    ref = ot.Table(32, 40, 5.0)
+    np.testing.assert_allclose(v[..., 0], ref.Tz, rtol=2e-7, atol=1e-9)
+    np.testing.assert_allclose(v[..., 1], ref.Tr, rtol=2e-7, atol=1e-9)
+    t.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_table_forces_match_oracle(sc, order):
+    p = synth.cylinder_load(1500, seed=41)
+    pos = p.pos.copy()
+    pos[0, :6] = 7.0 + 0.01 * np.arange(6)   # a few pairs beyond the table's rho_max
+    q = synth.Particles(pos, p.mass, p.eps, p.L)
+    t = sc.CorrectionTable(32, 40, 5.0, 1024)
+    acc, pot = sc.steps_cyl_forces_table(*to_dev(q), q.L, t, order=order)
+    torch.cuda.synchronize()
+    tg = np.unique(np.concatenate([np.arange(8), synth.target_sample(q.N, 60, seed=2)]))
+    ref = ot.forces_table(q.pos, q.mass, q.eps, q.L, ot.Table(32, 40, 5.0), order, targets=tg)
+    err = rel(acc[:, torch.from_numpy(tg).cuda()], ref)
+    print(f"order {order}: table scheme vs oracle max {err.max():.2e}")
+    assert err.max() <= 2e-5
+    t.close()
+
+
+def test_table_accuracy_against_exact_1024(sc):
+    p = synth.cylinder_load(1 << 16, seed=0)
+    pos, m, e = to_dev(p)
+    tt = torch.from_numpy(synth.target_sample(p.N, 1024, seed=5)).cuda()
+    truth, _ = sc.steps_cyl_forces_f64(pos, m, e, p.L, 1024, targets=tt, potential=False)
+    t = sc.CorrectionTable(128, 144, 6.4, 1024)
+    out = {}
+    for order in (1, 2):
+        a, _ = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order, targets=tt, potential=False)
+        out[order] = rel(a, truth)
+    a8, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=tt, potential=False)
+    e8 = rel(a8, truth)
+    for order, v in out.items():
+        print(f"table order {order}: max {v.max():.3e} median {np.median(v):.3e}")
+    print(f"|n|<=8: max {e8.max():.3e}")
+    assert out[1].max() < 0.05 * e8.max() and out[2].max() < 0.05 * e8.max()
+    t.close()
