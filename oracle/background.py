@@ -176,3 +176,51 @@ def kdk_step(pos, mom, mass, eps, L, n_img, a_begin, a_end, c, R, rho0, Z, acc=N
     comp = compensation(pos, R, Z, rho0) if compensate else 0.0
     mom = mom + K2 * (acc_new - comp)
     return pos, mom, acc_new
+
+
+# ---------------------------------------------------------------- tabulated history
+def history_interp(t_nodes, a_nodes, order, t):
+    """a(t) from a tabulated expansion history (Sect. 2.3: histories loaded from
+    a table and interpolated linearly, quadratically or cubically).  On the
+    interval [t_k, t_k+1] the interpolant is the Lagrange polynomial through
+    nodes k..k+1 (order 1), k..k+2 (order 2) or k-1..k+2 (order 3), the
+    stencil shifted inwards at the ends of the table."""
+    tn = np.asarray(t_nodes, dtype=np.float64)
+    an = np.asarray(a_nodes, dtype=np.float64)
+    n = tn.size
+    k = int(np.clip(np.searchsorted(tn, t, side="right") - 1, 0, n - 2))
+    first = {1: k, 2: k, 3: k - 1}[order]
+    first = int(np.clip(first, 0, n - 1 - order))
+    idx = range(first, first + order + 1)
+    val = 0.0
+    for p in idx:
+        w = 1.0
+        for q in idx:
+            if q != p:
+                w *= (t - tn[q]) / (tn[p] - tn[q])
+        val += w * an[p]
+    return val
+
+
+def history_factors(t_nodes, a_nodes, order, a_begin, a_end):
+    """(K1, D, K2) of one KDK step from a_begin to a_end on a tabulated history:
+    t(a) by root finding on the interpolant, then int dt/a and int dt/a^2 by
+    adaptive quadrature of the interpolant."""
+    from scipy import optimize
+    tn = np.asarray(t_nodes, dtype=np.float64)
+
+    def t_of(a):
+        return optimize.brentq(lambda t: history_interp(tn, a_nodes, order, t) - a, tn[0], tn[-1],
+                               xtol=1e-15, rtol=1e-15)
+
+    t0, t1 = t_of(a_begin), t_of(a_end)
+    tm = 0.5 * (t0 + t1)
+    pts = [x for x in tn if min(t0, t1) < x < max(t0, t1)]
+
+    def integ(lo, hi, p):
+        f = lambda t: history_interp(tn, a_nodes, order, t) ** (-p)
+        inner = [x for x in pts if min(lo, hi) < x < max(lo, hi)]
+        val, _ = integrate.quad(f, lo, hi, points=inner or None, epsabs=1e-15, epsrel=1e-13, limit=400)
+        return val
+
+    return integ(t0, tm, 1), integ(t0, t1, 2), integ(tm, t1, 1)

@@ -165,3 +165,31 @@ def test_kdk_is_time_reversible_and_conserves_momentum():
     dz = (x2 - p.pos)
     dz[2] -= np.round(dz[2])
     assert np.abs(dz).max() < 1e-12
+
+
+# ---------------------------------------------------------------- tabulated history
+def test_history_interpolation_orders_are_exact_on_polynomials():
+    t = np.linspace(0.0, 2.0, 9)
+    for order in (1, 2, 3):
+        a = 1.0 + 0.3 * t + (0.2 * t ** 2 if order >= 2 else 0) + (0.05 * t ** 3 if order >= 3 else 0)
+        for x in [0.0, 0.13, 0.77, 1.5, 1.99, 2.0]:
+            expect = 1.0 + 0.3 * x + (0.2 * x ** 2 if order >= 2 else 0) + (0.05 * x ** 3 if order >= 3 else 0)
+            assert bg.history_interp(t, a, order, x) == pytest.approx(expect, rel=1e-13)
+
+
+def test_history_factors_converge_to_closed_form():
+    # sampled from the flat-LCDM closed form; errors fall as h^(order+1)
+    c = lcdm()
+    ref = np.array(bg.kdk_factors(0.1, 0.11, c))
+    errs = {}
+    for n in (200, 400):
+        tt = np.linspace(bg.cosmic_time(0.05, c), bg.cosmic_time(0.5, c), n)
+        aa = np.array([bg.lcdm_scale_factor(x, c) for x in tt])
+        for order in (1, 2, 3):
+            got = np.array(bg.history_factors(tt, aa, order, 0.1, 0.11))
+            errs[(n, order)] = np.abs(got / ref - 1).max()
+    for order in (1, 2, 3):
+        assert errs[(200, order)] < 2e-4
+        ratio = errs[(200, order)] / errs[(400, order)]
+        # at least the pointwise order h^(order+1); integration can add one more
+        assert ratio > 0.7 * 2 ** (order + 1), (order, ratio)
