@@ -292,6 +292,9 @@ typedef struct {
     int compensate;          /* 1: subtract F_h; 0: pair forces only                        */
     int n_img;               /* exact images when net == NULL                               */
     const steps_cyl_mlp *net;  /* learned correction, or NULL for the exact sum            */
+    const double *factors;   /* host [3]: (K1, D, K2) to use instead of the Friedmann
+                                solution (e.g. from steps_cyl_history_factors), or NULL;
+                                the background fields are then not used             */
 } steps_cyl_kdk_params;
 
 /* Kick and drift factors of one step (host only, no device work):
@@ -301,6 +304,17 @@ typedef struct {
  * equation advanced by fourth-order Runge-Kutta.  STEPS_EDOMAIN if H^2 is
  * not positive over the step. */
 int steps_cyl_kdk_factors(const steps_cyl_kdk_params *params, double *out);
+
+/* Kick and drift factors on a tabulated expansion history (Sect. 2.3:
+ * histories given as a table, interpolated linearly, quadratically or
+ * cubically).  t[n], a[n] host arrays, both strictly increasing, a > 0;
+ * order 1, 2 or 3: on [t_k, t_k+1] the Lagrange polynomial through nodes
+ * k..k+1, k..k+2 or k-1..k+2 (shifted inwards at the table ends).  t(a) is
+ * found by bisection on the interpolant, the integrals by Gauss-Legendre on
+ * each piece.  out[3] as steps_cyl_kdk_factors.  STEPS_EDOMAIN if the step
+ * leaves the table.  Host only. */
+int steps_cyl_history_factors(const double *t, const double *a, int64_t n, int order,
+                              double a_begin, double a_end, double *out);
 
 /* F_h as a vector field at the particle positions: pos device [3][N] FP64,
  * out device [3][N] FP64 (radial in x, y; zero along z), G = 1. */

@@ -160,10 +160,12 @@ def lcdm_scale_factor(t, c):
 
 # ---------------------------------------------------------------- leapfrog
 def kdk_step(pos, mom, mass, eps, L, n_img, a_begin, a_end, c, R, rho0, Z, acc=None,
-             compensate=True):
+             compensate=True, factors=None):
     """One KDK step in FP64.  ``pos`` and ``mom`` are (3, N); ``acc`` the pair
-    acceleration at ``pos`` (computed when None).  Returns (pos, mom, acc_new)."""
-    K1, D, K2 = kdk_factors(a_begin, a_end, c)
+    acceleration at ``pos`` (computed when None); ``factors`` (K1, D, K2)
+    replaces the Friedmann solution (e.g. from ``history_factors``).  Returns
+    (pos, mom, acc_new)."""
+    K1, D, K2 = kdk_factors(a_begin, a_end, c) if factors is None else factors
     if acc is None:
         acc, _ = oracle.forces(pos, mass, eps, L, n_img, potential=False)
     comp = compensation(pos, R, Z, rho0) if compensate else 0.0

@@ -20,7 +20,7 @@ __all__ = [
     "steps_cyl_mlp_set_params", "steps_cyl_mlp_forward", "steps_cyl_mlp_grad",
     "steps_cyl_mlp_samples", "steps_cyl_mlp_train", "steps_cyl_mlp_save", "steps_cyl_mlp_load",
     "Mlp", "steps_cyl_forces_learned", "steps_cyl_forces_learned_ex",
-    "KdkParams", "steps_cyl_kdk_factors", "steps_cyl_compensation", "steps_cyl_kdk_step",
+    "KdkParams", "steps_cyl_kdk_factors", "steps_cyl_history_factors", "steps_cyl_compensation", "steps_cyl_kdk_step",
     "CorrectionTable", "steps_cyl_table_create", "steps_cyl_table_destroy",
     "steps_cyl_table_values", "steps_cyl_forces_table",
 ]
@@ -76,6 +76,7 @@ class KdkParams(ctypes.Structure):
         ("Omega_k", ctypes.c_double), ("w0", ctypes.c_double), ("wa", ctypes.c_double),
         ("R_cyl", ctypes.c_double), ("rho0", ctypes.c_double),
         ("compensate", ctypes.c_int), ("n_img", ctypes.c_int), ("net", ctypes.c_void_p),
+        ("factors", ctypes.c_void_p),
     ]
 
 
@@ -97,6 +98,7 @@ _SIGNATURES = {
     "steps_cyl_forces_learned": [_VP, _VP, _VP, _I64, _F64, _VP, _VP, _VP, _VP],
     "steps_cyl_forces_learned_ex": [_VP, _VP, _VP, _I64, _F64, _VP, _VP, _I64, _I32, _VP, _VP, _VP],
     "steps_cyl_kdk_factors": [ctypes.POINTER(KdkParams), _VP],
+    "steps_cyl_history_factors": [_VP, _VP, _I64, _I32, _F64, _F64, _VP],
     "steps_cyl_compensation": [_VP, _I64, _F64, _F64, _F64, _VP, _VP],
     "steps_cyl_kdk_step": [_VP, _VP, _VP, _VP, _I64, _F64, ctypes.POINTER(KdkParams), _VP, _VP],
     "steps_cyl_table_create": [_I32, _I32, _F64, _I32, _VP, _PP],
@@ -418,10 +420,32 @@ def steps_cyl_forces_learned_ex(pos, mass, eps, L, net, targets=None, mode=STEPS
 
 
 # ---------------------------------------------------------------- time integration
+_FACTOR_KEEP = []
+
+
 def kdk_params(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r=0.0, Omega_k=0.0, w0=-1.0, wa=0.0,
-               R_cyl=1.0, rho0=0.0, compensate=True, n_img=8, net=None):
+               R_cyl=1.0, rho0=0.0, compensate=True, n_img=8, net=None, factors=None):
+    fp = None
+    if factors is not None:
+        arr = (ctypes.c_double * 3)(*[float(x) for x in factors])
+        _FACTOR_KEEP.append(arr)
+        del _FACTOR_KEEP[:-64]
+        fp = ctypes.cast(arr, ctypes.c_void_p)
     return KdkParams(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r, Omega_k, w0, wa, R_cyl, rho0,
-                     1 if compensate else 0, int(n_img), _handle(net) if net is not None else None)
+                     1 if compensate else 0, int(n_img), _handle(net) if net is not None else None,
+                     fp)
+
+
+def steps_cyl_history_factors(t, a, order, a_begin, a_end):
+    """(K1, D, K2) of one step on a tabulated history (host computation)."""
+    import numpy as np
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    out = (ctypes.c_double * 3)()
+    _check(lib().steps_cyl_history_factors(t.ctypes.data, a.ctypes.data, t.size, int(order),
+                                           float(a_begin), float(a_end),
+                                           ctypes.cast(out, ctypes.c_void_p)))
+    return tuple(out)
 
 
 def steps_cyl_kdk_factors(params):

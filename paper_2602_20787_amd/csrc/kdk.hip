@@ -91,6 +91,20 @@ const Quad &theta_rule() {
     return q;
 }
 
+struct Rule16 {
+    double x[16], w[16];  // on [-1, 1]
+};
+
+// initialised once, thread-safe (function-local static)
+const Rule16 &rule16() {
+    static const Rule16 r = [] {
+        Rule16 q;
+        gauss_legendre(16, q.x, q.w);
+        return q;
+    }();
+    return r;
+}
+
 struct CompArgs {
     Quad q;
     double R, Z, rho0;  // G = 1
@@ -166,12 +180,8 @@ struct Background {
 
 // t(a1) - t(a0) = int_{ln a0}^{ln a1} dln a / H(a), composite Gauss-Legendre
 double step_length(const Background &bg, double a0, double a1) {
-    static double x[16], w[16];
-    static bool init = false;
-    if (!init) {
-        gauss_legendre(16, x, w);
-        init = true;
-    }
+    const Rule16 &g = rule16();
+    const double *x = g.x, *w = g.w;
     const double l0 = std::log(a0), l1 = std::log(a1);
     const int panels = 64;
     const double hw = (l1 - l0) / panels;
@@ -208,6 +218,15 @@ void advance(const Background &bg, double a0, double span, int n_sub, double out
 
 int check_params(const steps_cyl_kdk_params *p) {
     if (!p) return fail(STEPS_EINVAL, "params must be non-null");
+    if (p->factors) {
+        for (int q = 0; q < 3; ++q)
+            if (!std::isfinite(p->factors[q])) return fail(STEPS_EINVAL, "non-finite step factor");
+        if (p->compensate && (!finite_positive(p->R_cyl) || !std::isfinite(p->rho0) || p->rho0 < 0.0))
+            return fail(STEPS_EINVAL, "compensation needs R_cyl > 0 and rho0 >= 0");
+        if (!p->net && (p->n_img < 0 || p->n_img > STEPS_MAX_NIMG))
+            return fail(STEPS_EINVAL, "n_img=%d outside [0, %d]", p->n_img, STEPS_MAX_NIMG);
+        return STEPS_OK;
+    }
     const double v[] = {p->a_begin, p->a_end, p->H0, p->Omega_m, p->Omega_L, p->Omega_r, p->Omega_k, p->w0, p->wa};
     for (double x : v)
         if (!std::isfinite(x)) return fail(STEPS_EINVAL, "non-finite background parameter");
@@ -229,6 +248,12 @@ int check_params(const steps_cyl_kdk_params *p) {
 }
 
 void factors(const steps_cyl_kdk_params *p, double out[3]) {
+    if (p->factors) {
+        out[0] = p->factors[0];
+        out[1] = p->factors[1];
+        out[2] = p->factors[2];
+        return;
+    }
     Background bg{p->H0, p->Omega_m, p->Omega_L, p->Omega_r, p->Omega_k, p->w0, p->wa};
     const double dt = step_length(bg, p->a_begin, p->a_end);
     double h1[3], h2[3];
@@ -238,6 +263,62 @@ void factors(const steps_cyl_kdk_params *p, double out[3]) {
     out[1] = h1[2] + h2[2];
     out[2] = h2[1];
 }
+
+// ---------------------------------------------------------------- tabulated history
+// a(t) on [t_k, t_k+1]: Lagrange polynomial through nodes k..k+1 (order 1),
+// k..k+2 (order 2) or k-1..k+2 (order 3), shifted inwards at the table ends.
+struct History {
+    const double *t, *a;
+    int64_t n;
+    int order;
+    double eval(double x) const {
+        int64_t lo = 0, hi = n - 1;  // k: last node with t_k <= x, clamped to [0, n-2]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) / 2;
+            if (t[mid] <= x) lo = mid; else hi = mid;
+        }
+        int64_t k = lo;
+        if (k > n - 2) k = n - 2;
+        int64_t first = (order == 3) ? k - 1 : k;
+        if (first > n - 1 - order) first = n - 1 - order;
+        if (first < 0) first = 0;
+        double v = 0.0;
+        for (int64_t p = first; p <= first + order; ++p) {
+            double w = 1.0;
+            for (int64_t q = first; q <= first + order; ++q)
+                if (q != p) w *= (x - t[q]) / (t[p] - t[q]);
+            v += w * a[p];
+        }
+        return v;
+    }
+    // t with a(t) = target by bisection on the (monotonic) interpolant
+    double invert(double target) const {
+        double lo = t[0], hi = t[n - 1];
+        for (int it = 0; it < 200 && hi - lo > 1e-15 * std::fabs(hi); ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (eval(mid) < target) lo = mid; else hi = mid;
+        }
+        return 0.5 * (lo + hi);
+    }
+    // int_{x0}^{x1} a(t)^-p dt: 16-point Gauss-Legendre on every piece between nodes
+    double integral(double x0, double x1, int p) const {
+        const Rule16 &g = rule16();
+        const double *gx = g.x, *gw = g.w;
+        const double sgn = x1 >= x0 ? 1.0 : -1.0;
+        const double lo = std::fmin(x0, x1), hi = std::fmax(x0, x1);
+        double sum = 0.0, a0 = lo;
+        int64_t k = 0;
+        while (k < n && t[k] <= lo) ++k;
+        while (a0 < hi) {
+            const double b0 = (k < n && t[k] < hi) ? t[k] : hi;
+            const double hw = 0.5 * (b0 - a0), mid = 0.5 * (a0 + b0);
+            for (int i = 0; i < 16; ++i) sum += hw * gw[i] * std::pow(eval(mid + hw * gx[i]), -p);
+            a0 = b0;
+            ++k;
+        }
+        return sgn * sum;
+    }
+};
 
 CompArgs comp_args(double R, double Z, double rho0) {
     CompArgs c;
@@ -259,6 +340,29 @@ STEPS_API int steps_cyl_kdk_factors(const steps_cyl_kdk_params *params, double *
     if (!out) return fail(STEPS_EINVAL, "out must be non-null");
     clear_error();
     factors(params, out);
+    return STEPS_OK;
+}
+
+STEPS_API int steps_cyl_history_factors(const double *t, const double *a, int64_t n, int order,
+                                        double a_begin, double a_end, double *out) {
+    if (!t || !a || !out) return fail(STEPS_EINVAL, "t, a and out must be non-null");
+    if (order < 1 || order > 3) return fail(STEPS_EINVAL, "order=%d: 1, 2 or 3", order);
+    if (n < order + 1) return fail(STEPS_EINVAL, "n=%lld: at least order+1 nodes", (long long)n);
+    for (int64_t k = 0; k < n; ++k) {
+        if (!std::isfinite(t[k]) || !std::isfinite(a[k]) || !(a[k] > 0.0))
+            return fail(STEPS_EINVAL, "node %lld is not finite or has a <= 0", (long long)k);
+        if (k > 0 && !(t[k] > t[k - 1] && a[k] > a[k - 1]))
+            return fail(STEPS_EINVAL, "t and a must increase strictly (node %lld)", (long long)k);
+    }
+    const double lo = std::fmin(a_begin, a_end), hi = std::fmax(a_begin, a_end);
+    if (!(lo >= a[0] && hi <= a[n - 1]))
+        return fail(STEPS_EDOMAIN, "the step [%g, %g] leaves the table [%g, %g]", a_begin, a_end, a[0], a[n - 1]);
+    clear_error();
+    const History H{t, a, n, order};
+    const double t0 = H.invert(a_begin), t1 = H.invert(a_end), tm = 0.5 * (t0 + t1);
+    out[0] = H.integral(t0, tm, 1);
+    out[1] = H.integral(t0, t1, 2);
+    out[2] = H.integral(tm, t1, 1);
     return STEPS_OK;
 }
 

@@ -141,3 +141,30 @@ def test_learned_steps_follow_exact_1024(sc):
     print(f"learned vs exact-1024 momenta after 4 steps: max {d.max():.2e} median {np.median(d):.2e}")
     assert d.max() <= 1e-4
     net.close()
+
+
+def test_step_on_tabulated_history_matches_oracle(sc):
+    # the background as a table (cubic), factors on the host, the step on the GPU
+    p = synth.displaced_load(1024, seed=7)
+    c, R, rho0 = cosmo_for_load()
+    tt = np.linspace(bg.cosmic_time(0.03, c), bg.cosmic_time(0.1, c), 40)
+    aa = np.array([bg.lcdm_scale_factor(x, c) for x in tt])
+    fac = sc.steps_cyl_history_factors(tt, aa, 3, 0.05, 0.06)
+    ref_fac = bg.history_factors(tt, aa, 3, 0.05, 0.06)
+    np.testing.assert_allclose(fac, ref_fac, rtol=1e-10)
+    pos, mom, m, e, acc = _state(sc, p)
+    mom0 = 0.02 * np.random.default_rng(8).standard_normal((3, p.N))
+    mom.copy_(dev(mom0))
+    # background fields deliberately nonsense: only the factors may be used
+    par = sc.kdk_params(0.05, 0.06, -1.0, -1.0, -1.0, R_cyl=R, rho0=rho0, n_img=8, factors=fac)
+    sc.steps_cyl_kdk_step(pos, mom, m, e, p.L, par, acc)
+    torch.cuda.synchronize()
+    x_ref, p_ref, a_ref = bg.kdk_step(p.pos, mom0, p.mass, p.eps, p.L, 8, 0.05, 0.06, c, R, rho0, 8.5,
+                                      factors=ref_fac)
+    kick = (fac[0] + fac[2]) * np.abs(a_ref).max()
+    assert np.abs(mom.cpu().numpy() - p_ref).max() <= 2e-5 * kick
+    dx = pos.cpu().numpy() - x_ref
+    dx[2] -= np.round(dx[2])
+    assert np.abs(dx).max() <= 2e-5 * kick * fac[1] + 1e-14
+    # and the table reproduces the Friedmann step it was sampled from
+    np.testing.assert_allclose(fac, bg.kdk_factors(0.05, 0.06, c), rtol=1e-6)

@@ -53,3 +53,52 @@ def test_kdk_step_rejects_bad_arguments():
     bad = sc.kdk_params(0.1, 0.2, 1.0, 0.3, 0.7, R_cyl=3.0, rho0=0.03, n_img=5000)
     assert L.steps_cyl_kdk_step(P, P, P, P, 10, 1.0, ctypes.byref(bad), P, None) == sc.STEPS_EINVAL
     assert L.steps_cyl_compensation(P, 10, -1.0, 8.5, 0.03, P, None) == sc.STEPS_EINVAL
+
+
+# ---------------------------------------------------------------- tabulated history
+def _lcdm_table(n):
+    import numpy as np
+    c = bg.Cosmology(H0=0.944, Om=0.3, OL=0.7)
+    tt = np.linspace(bg.cosmic_time(0.05, c), bg.cosmic_time(0.5, c), n)
+    aa = np.array([bg.lcdm_scale_factor(x, c) for x in tt])
+    return tt, aa
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_history_factors_match_oracle(order):
+    tt, aa = _lcdm_table(60)
+    got = sc.steps_cyl_history_factors(tt, aa, order, 0.1, 0.13)
+    ref = bg.history_factors(tt, aa, order, 0.1, 0.13)
+    for g, r in zip(got, ref):
+        assert g == pytest.approx(r, rel=1e-10)
+    # reversed step
+    got_r = sc.steps_cyl_history_factors(tt, aa, order, 0.13, 0.1)
+    assert got_r[0] == pytest.approx(-got[2], rel=1e-9) and got_r[1] == pytest.approx(-got[1], rel=1e-9)
+
+
+def test_history_factors_validation():
+    import numpy as np
+    tt, aa = _lcdm_table(10)
+    with pytest.raises(sc.StepsError) as e:
+        sc.steps_cyl_history_factors(tt, aa, 4, 0.1, 0.2)
+    assert e.value.code == sc.STEPS_EINVAL
+    with pytest.raises(sc.StepsError) as e:
+        sc.steps_cyl_history_factors(tt, aa, 1, 0.01, 0.2)
+    assert e.value.code == sc.STEPS_EDOMAIN
+    bad = aa.copy()
+    bad[4] = bad[3]
+    with pytest.raises(sc.StepsError) as e:
+        sc.steps_cyl_history_factors(tt, bad, 1, 0.1, 0.2)
+    assert e.value.code == sc.STEPS_EINVAL
+    with pytest.raises(sc.StepsError):
+        sc.steps_cyl_history_factors(tt[:2], aa[:2], 3, 0.06, 0.07)
+
+
+def test_explicit_factors_pass_through():
+    # with factors given the background is not read (even nonsense values pass)
+    p = sc.kdk_params(0.1, 0.2, -1.0, -1.0, -1.0, factors=(0.5, 0.25, 0.125))
+    assert sc.steps_cyl_kdk_factors(p) == (0.5, 0.25, 0.125)
+    bad = sc.kdk_params(0.1, 0.2, 1.0, 0.3, 0.7, factors=(0.5, float("nan"), 0.1))
+    with pytest.raises(sc.StepsError) as e:
+        sc.steps_cyl_kdk_factors(bad)
+    assert e.value.code == sc.STEPS_EINVAL
