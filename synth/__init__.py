@@ -52,18 +52,41 @@ def _softening(mass):
     return 0.01 * np.cbrt(mass / mass.min())
 
 
-def cylinder_load(N, seed=0, L=1.0, R0=R0_DEFAULT, chi_max=CHI_MAX_DEFAULT):
+def cylinder_load(N, seed=0, L=1.0, R0=R0_DEFAULT, chi_max=CHI_MAX_DEFAULT, omega_c=0.0):
     """Stereographic cylinder load of ``N`` particles (total mass 1).
 
-    Draw order from ``default_rng(seed)``: z (N), azimuth (N), radial variate (N).
+    ``omega_c`` > 0 adds the constant-resolution core of the paper's load
+    (Sect. 3.1): inside the compact radius omega_c (physical radius
+    rho_c = R0 tan(omega_c/2)) particles are uniform in area with the mass the
+    outer law takes at rho_c; outside, the compact coordinate follows the
+    sin(chi) law on [omega_c, chi_max).  The core holds the share of particles
+    that keeps the number density continuous at rho_c,
+        N_core / N_out = sin^2(omega_c) / (2 (cos omega_c - cos chi_max)),
+    so the mass density stays flat across the core boundary.
+
+    Draw order from ``default_rng(seed)``: z (N), azimuth (N), radial variate
+    (N; the first N_core of them place the core particles).
     """
     rng = np.random.default_rng(seed)
     z = rng.random(N) * L
     phi = rng.random(N) * (2.0 * math.pi)
     u = rng.random(N)
-    r = _radius_from_u(u, R0, chi_max)
+    if omega_c > 0.0:
+        if not omega_c < chi_max:
+            raise ValueError("omega_c must lie below chi_max")
+        ratio = math.sin(omega_c) ** 2 / (2.0 * (math.cos(omega_c) - math.cos(chi_max)))
+        n_core = int(round(N * ratio / (1.0 + ratio)))
+        rho_c = R0 * math.tan(0.5 * omega_c)
+        r = np.empty(N)
+        r[:n_core] = rho_c * np.sqrt(u[:n_core])
+        cc = math.cos(omega_c)
+        chi = np.arccos(cc - u[n_core:] * (cc - math.cos(chi_max)))
+        r[n_core:] = R0 * np.tan(0.5 * chi)
+        m = _mass_law(np.maximum(r, rho_c), R0)
+    else:
+        r = _radius_from_u(u, R0, chi_max)
+        m = _mass_law(r, R0)
     pos = np.stack([r * np.cos(phi), r * np.sin(phi), z])
-    m = _mass_law(r, R0)
     m /= m.sum()
     return Particles(pos, m, _softening(m), L)
 

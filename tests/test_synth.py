@@ -81,3 +81,27 @@ def test_remainder_inputs_cover_the_network_domain():
 def test_targets_are_distinct_and_sorted():
     t = synth.target_sample(1000, 300, seed=4)
     assert len(np.unique(t)) == 300 and np.all(np.diff(t) > 0) and t.max() < 1000
+
+
+def test_core_load_is_flat_with_constant_core_masses():
+    # constant-resolution core (Sect. 3.1): equal masses inside rho_c, the
+    # outer mass law outside, and the mass density flat across the boundary
+    omega_c = 1.2
+    N = 200000
+    p = synth.cylinder_load(N, seed=2, omega_c=omega_c)
+    r = np.hypot(p.pos[0], p.pos[1])
+    rho_c = 0.5 * math.tan(0.5 * omega_c)
+    core = r < rho_c
+    np.testing.assert_array_equal(p.mass[core], p.mass[core][0])
+    assert p.mass[~core].min() >= p.mass[core][0] * (1 - 1e-12)
+    assert abs(p.mass.sum() - 1.0) < 1e-12 and r.max() <= synth.r_max()
+    edges = np.concatenate([np.linspace(0.0, rho_c, 5), np.linspace(rho_c, 3.0, 9)[1:]])
+    mean = 1.0 / (math.pi * synth.r_max() ** 2)
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = (r >= lo) & (r < hi)
+        dens = p.mass[sel].sum() / (math.pi * (hi * hi - lo * lo))
+        assert abs(dens / mean - 1.0) < 0.06, (lo, hi, dens / mean)
+    # omega_c = 0 is the plain load, draw for draw
+    q = synth.cylinder_load(1000, seed=3, omega_c=0.0)
+    q0 = synth.cylinder_load(1000, seed=3)
+    np.testing.assert_array_equal(q.pos, q0.pos)
