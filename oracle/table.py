@@ -23,6 +23,10 @@ TSC: the nearest node k and its neighbours with weights
     w_{k-1} = (1/2 - f)^2 / 2,  w_k = 3/4 - f^2,  w_{k+1} = (1/2 + f)^2 / 2,
     f = x - k in [-1/2, 1/2], per axis, product over the two axes.
 Pairs with r > r_max use the exact band.
+
+A table of the complete correction (every image |n| >= 2, N_cut -> inf) is
+built from the Ewald split of ``oracle.ewald`` (``Table.ewald``); its pairs
+beyond r_max take the complete band from ``oracle.ewald.band_direct``.
 """
 from __future__ import annotations
 
@@ -34,16 +38,40 @@ N_FAR = 1024
 
 
 class Table:
-    def __init__(self, n_d, n_r, r_max, n_far=N_FAR):
+    def __init__(self, n_d, n_r, r_max, n_far=N_FAR, _nodes=None):
         self.n_d, self.n_r, self.r_max, self.n_far = int(n_d), int(n_r), float(r_max), int(n_far)
         self.h_d = 0.5 / self.n_d
         self.h_r = self.r_max / self.n_r
-        di = np.arange(-1, self.n_d + 2) * self.h_d
-        rj = np.arange(-1, self.n_r + 2) * self.h_r
-        D, R = np.meshgrid(di, rj)              # [j][i]
-        fz, fr, _ = oracle.image_band(D.ravel(), R.ravel(), 1.0, 2, self.n_far)
+        self.complete = _nodes is not None
+        D, R = self.grid()
+        if _nodes is None:
+            fz, fr, _ = oracle.image_band(D.ravel(), R.ravel(), 1.0, 2, self.n_far)
+        else:
+            fz, fr = _nodes(D.ravel(), R.ravel())
         self.Tz = fz.reshape(D.shape)           # index [j + 1][i + 1]
         self.Tr = fr.reshape(D.shape)
+
+    def grid(self):
+        """Node coordinates (delta, r), each [n_r + 3][n_d + 3]."""
+        di = np.arange(-1, self.n_d + 2) * self.h_d
+        rj = np.arange(-1, self.n_r + 2) * self.h_r
+        return np.meshgrid(di, rj)
+
+    @classmethod
+    def ewald(cls, n_d, n_r, r_max, alpha, n_max, m_max, kernel="corrected"):
+        """Table of the complete band (|n| >= 2) by the Ewald split; nodes at
+        negative r take the odd/even continuation (T_rho odd, T_z even)."""
+        from oracle import ewald as ew
+
+        def nodes(D, R):
+            fz = np.empty(D.size)
+            fr = np.empty(D.size)
+            for q, (d, r) in enumerate(zip(D, R)):
+                z, p = ew.band_ewald(d, abs(r), alpha, n_max, m_max, kernel)
+                fz[q] = z
+                fr[q] = p if r >= 0 else -p
+            return fz, fr
+        return cls(n_d, n_r, r_max, 0, _nodes=nodes)
 
 
 def _node(T, j, i):
@@ -112,7 +140,11 @@ def forces_table(pos, mass, eps, L, tab, order, targets=None):
             Fr[inside] = tr
         out = ~inside
         if out.any():
-            Fz[out], Fr[out], _ = oracle.image_band(d[out] / L, r[out], 1.0, 2, tab.n_far)
+            if tab.complete:
+                from oracle import ewald as ew
+                Fz[out], Fr[out] = ew.band_direct(d[out] / L, r[out])
+            else:
+                Fz[out], Fr[out], _ = oracle.image_band(d[out] / L, r[out], 1.0, 2, tab.n_far)
         m = mass[j] / (L * L)
         with np.errstate(invalid="ignore", divide="ignore"):
             ux = np.where(rho > 0, dx / rho, 0.0)
