@@ -237,19 +237,45 @@ int steps_cyl_forces_learned_ex(const double *pos, const double *mass, const dou
  * Tabulated far-image correction (Sect. 2.2, eq. S1R2EwaldCorrectionTable:
  * a correction tabulated on an equally spaced grid in the cylindrical
  * coordinates, interpolated with CIC or TSC and added to the nearest-image
- * forces).  The table holds the image band 2 <= |n| <= n_far of one unit
- * mass, T = (T_z, T_rho) per G m / L^2, at delta = |d|/L = i/(2 n_delta)
+ * forces).  A table holds an image band of one unit mass,
+ * T = (T_z, T_rho) per G m / L^2, at delta = |d|/L = i/(2 n_delta)
  * (i = -1..n_delta+1) and r = rho/L = j rho_max/n_rho (j = -1..n_rho+1),
  * computed in FP64 and stored in FP32; R_z = sign(d) T_z, R_rho = T_rho.
- * Pairs with rho/L > rho_max use the exact band.  The table is in units of
- * L, so one table serves every period.
+ * The table is in units of L, so one table serves every period.
+ *   band table:     the images 2 <= |n| <= n_far, summed directly; pairs
+ *                   with rho/L > rho_max use the exact band.
+ *   complete table: every image |n| >= 2 (N_cut -> infinity), from the
+ *                   Ewald split (Sect. 2.2, eqs. cylindricalEwaldSplit,
+ *                   EwaldRealSum, EwaldRecSum); pairs with rho/L > rho_max
+ *                   use the line-mass limit F_rho = -2 G m/(L rho) of the
+ *                   complete sum (its modes decay as exp(-2 pi rho/L)).
  * ---------------------------------------------------------------------- */
 typedef struct steps_cyl_table steps_cyl_table;   /* opaque; owns device memory */
 
-/* Builds a table (device memory owned by the handle; synchronises stream).
- * 2 <= n_delta, n_rho <= 4096; 0 < rho_max <= 1e4; 2 <= n_far <= 2^20. */
+#define STEPS_TABLE_MAX_FAR (1 << 24)
+
+/* Builds a band table (device memory owned by the handle; synchronises
+ * stream).  2 <= n_delta, n_rho <= 4096; 0 < rho_max <= 1e4;
+ * 2 <= n_far <= STEPS_TABLE_MAX_FAR (n_far = 10^7 is the direct reference of
+ * Fig. 2). */
 int steps_cyl_table_create(int n_delta, int n_rho, double rho_max, int n_far,
                            hipStream_t stream, steps_cyl_table **out);
+
+/* Fourier kernels of the Ewald split. */
+#define STEPS_EWALD_BESSEL  0   /* B(k,rho) = int_{1/(4 alpha^2)}^inf exp(-k^2 t - rho^2/(4t)) dt/(2t),
+                                   force (4/L) grad[cos(k d) B]: the Poisson sum of the smooth
+                                   part for one periodic direction (exact for any alpha)     */
+#define STEPS_EWALD_PRINTED 1   /* the kernel of eq. Bkernel with its printed prefactor
+                                   -(2/L); matches the complete sum only where its modes
+                                   are negligible (alpha scans of Fig. 2)                    */
+
+/* Builds a complete table from the Ewald split with splitting parameter
+ * alpha (per 1/L) in (0, 64], real-space images n = -n_max..n_max
+ * (1 <= n_max <= 1024) and modes m = 1..m_max (0 <= m_max <= 1024);
+ * rho_max >= 4; other arguments as steps_cyl_table_create. */
+int steps_cyl_table_create_ewald(int n_delta, int n_rho, double rho_max, double alpha,
+                                 int n_max, int m_max, int kernel, hipStream_t stream,
+                                 steps_cyl_table **out);
 
 /* Releases a table (NULL is ignored). */
 void steps_cyl_table_destroy(steps_cyl_table *table);
@@ -257,6 +283,13 @@ void steps_cyl_table_destroy(steps_cyl_table *table);
 /* Copies the nodes to host_out[(n_rho+3) * (n_delta+3) * 2] FP32, node
  * (i, j) at ((j+1) * (n_delta+3) + i+1) * 2 as (T_z, T_rho) (synchronous). */
 int steps_cyl_table_values(const steps_cyl_table *table, float *host_out);
+
+/* The same nodes in FP64, as built (synchronous). */
+int steps_cyl_table_values_f64(const steps_cyl_table *table, double *host_out);
+
+/* Grid of a table; *n_far = -1 for a complete table.  Any output may be NULL. */
+int steps_cyl_table_info(const steps_cyl_table *table, int *n_delta, int *n_rho,
+                         double *rho_max, int *n_far);
 
 /* Accelerations with the exact images |n| <= 1 (spline-softened) plus the
  * interpolated band (order 1 = CIC, 2 = TSC); out_pot, when non-NULL, gets
@@ -276,8 +309,10 @@ int steps_cyl_forces_table(const double *pos, const double *mass, const double *
  *     dp/dt = (g(x) - F_h(x)) / a,   dx/dt = p / a^2,
  * g the pair-sum acceleration of the force entry points (G = 1, a = 1) and
  * F_h the radial field of the homogeneous cylinder (radius R_cyl, comoving
- * density rho0, half-height Z = (n_img + 1/2) L, or 1024.5 L with a
- * network) that the truncated image sum adds to every particle.  F_h is
+ * density rho0, half-height Z = (n_img + 1/2) L; 1024.5 L with a network;
+ * (n_far + 1/2) L with a band table; infinite with a complete table, where
+ * F_h = -2 pi G rho0 rho inside R_cyl, eq. F_horiz_infty) that the image
+ * sum adds to every particle.  F_h is
  * evaluated from the line-element integral over disk chords (the form that
  * tends to -2 pi G rho0 rho as Z -> infinity; the paper's printed
  * finite-height formula has the opposite sign and half of the logarithmic
@@ -295,6 +330,8 @@ typedef struct {
     const double *factors;   /* host [3]: (K1, D, K2) to use instead of the Friedmann
                                 solution (e.g. from steps_cyl_history_factors), or NULL;
                                 the background fields are then not used             */
+    const steps_cyl_table *table;  /* tabulated correction (net must be NULL), or NULL   */
+    int table_order;         /* 1 = CIC, 2 = TSC, with a table                              */
 } steps_cyl_kdk_params;
 
 /* Kick and drift factors of one step (host only, no device work):
@@ -317,7 +354,10 @@ int steps_cyl_history_factors(const double *t, const double *a, int64_t n, int o
                               double a_begin, double a_end, double *out);
 
 /* F_h as a vector field at the particle positions: pos device [3][N] FP64,
- * out device [3][N] FP64 (radial in x, y; zero along z), G = 1. */
+ * out device [3][N] FP64 (radial in x, y; zero along z), G = 1.  Z > 0 is
+ * the half-height; Z = +infinity gives the infinite cylinder,
+ * -2 pi G rho0 rho inside R_cyl (eq. F_horiz_infty) and -2 pi G rho0 R^2/rho
+ * outside. */
 int steps_cyl_compensation(const double *pos, int64_t N, double R_cyl, double Z, double rho0,
                            double *out, hipStream_t stream);
 

@@ -64,7 +64,8 @@ def cylinder_field(rho, R, Z, rho0, G=1.0):
         return math.log(wp / wm)
 
     brk = [0.0] if abs(rho - R) < 1e-12 else None
-    A, _ = integrate.quad(fa, 0.0, R, epsabs=1e-15, epsrel=1e-12, limit=400)
+    # the end-cap term vanishes for an infinite cylinder (Z -> inf)
+    A = 0.0 if math.isinf(Z) else integrate.quad(fa, 0.0, R, epsabs=1e-15, epsrel=1e-12, limit=400)[0]
     B, _ = integrate.quad(fb, 0.0, R, epsabs=1e-15, epsrel=1e-12, limit=400, points=brk)
     return 2.0 * G * rho0 * (2.0 * A - B)
 

@@ -22,7 +22,8 @@ __all__ = [
     "Mlp", "steps_cyl_forces_learned", "steps_cyl_forces_learned_ex",
     "KdkParams", "steps_cyl_kdk_factors", "steps_cyl_history_factors", "steps_cyl_compensation", "steps_cyl_kdk_step",
     "CorrectionTable", "steps_cyl_table_create", "steps_cyl_table_destroy",
-    "steps_cyl_table_values", "steps_cyl_forces_table",
+    "steps_cyl_table_values", "steps_cyl_forces_table", "steps_cyl_table_create_ewald",
+    "steps_cyl_table_values_f64", "steps_cyl_table_info", "STEPS_EWALD_BESSEL", "STEPS_EWALD_PRINTED",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -76,7 +77,7 @@ class KdkParams(ctypes.Structure):
         ("Omega_k", ctypes.c_double), ("w0", ctypes.c_double), ("wa", ctypes.c_double),
         ("R_cyl", ctypes.c_double), ("rho0", ctypes.c_double),
         ("compensate", ctypes.c_int), ("n_img", ctypes.c_int), ("net", ctypes.c_void_p),
-        ("factors", ctypes.c_void_p),
+        ("factors", ctypes.c_void_p), ("table", ctypes.c_void_p), ("table_order", ctypes.c_int),
     ]
 
 
@@ -103,6 +104,9 @@ _SIGNATURES = {
     "steps_cyl_kdk_step": [_VP, _VP, _VP, _VP, _I64, _F64, ctypes.POINTER(KdkParams), _VP, _VP],
     "steps_cyl_table_create": [_I32, _I32, _F64, _I32, _VP, _PP],
     "steps_cyl_table_values": [_VP, _VP],
+    "steps_cyl_table_create_ewald": [_I32, _I32, _F64, _F64, _I32, _I32, _I32, _VP, _PP],
+    "steps_cyl_table_values_f64": [_VP, _VP],
+    "steps_cyl_table_info": [_VP, _VP, _VP, _VP, _VP],
     "steps_cyl_forces_table": [_VP, _VP, _VP, _I64, _F64, _VP, _I32, _VP, _I64, _VP, _VP, _VP],
 }
 
@@ -424,7 +428,8 @@ _FACTOR_KEEP = []
 
 
 def kdk_params(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r=0.0, Omega_k=0.0, w0=-1.0, wa=0.0,
-               R_cyl=1.0, rho0=0.0, compensate=True, n_img=8, net=None, factors=None):
+               R_cyl=1.0, rho0=0.0, compensate=True, n_img=8, net=None, factors=None, table=None,
+               table_order=2):
     fp = None
     if factors is not None:
         arr = (ctypes.c_double * 3)(*[float(x) for x in factors])
@@ -433,7 +438,8 @@ def kdk_params(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r=0.0, Omega_k=0.0, w
         fp = ctypes.cast(arr, ctypes.c_void_p)
     return KdkParams(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r, Omega_k, w0, wa, R_cyl, rho0,
                      1 if compensate else 0, int(n_img), _handle(net) if net is not None else None,
-                     fp)
+                     fp, (table.handle if isinstance(table, CorrectionTable) else table) if table is not None
+                     else None, int(table_order))
 
 
 def steps_cyl_history_factors(t, a, order, a_begin, a_end):
@@ -500,12 +506,53 @@ def steps_cyl_table_values(handle, n_delta, n_rho):
     return out
 
 
-class CorrectionTable:
-    """Owning wrapper of a table handle."""
+STEPS_EWALD_BESSEL = 0
+STEPS_EWALD_PRINTED = 1
 
-    def __init__(self, n_delta=128, n_rho=144, rho_max=6.4, n_far=1024):
-        self.n_delta, self.n_rho, self.rho_max, self.n_far = n_delta, n_rho, rho_max, n_far
-        self.handle = steps_cyl_table_create(n_delta, n_rho, rho_max, n_far)
+
+def steps_cyl_table_create_ewald(n_delta=128, n_rho=144, rho_max=6.4, alpha=2.0, n_max=5, m_max=12,
+                                 kernel=STEPS_EWALD_BESSEL, stream=None):
+    import torch
+    h = ctypes.c_void_p()
+    _check(lib().steps_cyl_table_create_ewald(int(n_delta), int(n_rho), float(rho_max), float(alpha),
+                                              int(n_max), int(m_max), int(kernel),
+                                              _stream(stream, torch.device("cuda:0")), ctypes.byref(h)))
+    return h.value
+
+
+def steps_cyl_table_values_f64(handle, n_delta, n_rho):
+    """Nodes as an FP64 array (n_rho + 3, n_delta + 3, 2)."""
+    import numpy as np
+    out = np.empty((n_rho + 3, n_delta + 3, 2), dtype=np.float64)
+    _check(lib().steps_cyl_table_values_f64(handle, out.ctypes.data))
+    return out
+
+
+def steps_cyl_table_info(handle):
+    """(n_delta, n_rho, rho_max, n_far); n_far = -1 for a complete table."""
+    nd, nr, nf = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    rm = ctypes.c_double()
+    _check(lib().steps_cyl_table_info(handle, ctypes.byref(nd), ctypes.byref(nr), ctypes.byref(rm),
+                                      ctypes.byref(nf)))
+    return nd.value, nr.value, rm.value, nf.value
+
+
+class CorrectionTable:
+    """Owning wrapper of a table handle: a band table of the images
+    2 <= |n| <= n_far, or (``CorrectionTable.ewald``) a complete table."""
+
+    def __init__(self, n_delta=128, n_rho=144, rho_max=6.4, n_far=1024, _handle=None):
+        if _handle is None:
+            _handle = steps_cyl_table_create(n_delta, n_rho, rho_max, n_far)
+        self.handle = _handle
+        self.n_delta, self.n_rho, self.rho_max, self.n_far = steps_cyl_table_info(_handle)
+        self.complete = self.n_far < 0
+
+    @classmethod
+    def ewald(cls, n_delta=128, n_rho=144, rho_max=6.4, alpha=2.0, n_max=5, m_max=12,
+              kernel=STEPS_EWALD_BESSEL):
+        return cls(_handle=steps_cyl_table_create_ewald(n_delta, n_rho, rho_max, alpha, n_max, m_max,
+                                                        kernel))
 
     def close(self):
         if self.handle:
@@ -520,6 +567,9 @@ class CorrectionTable:
 
     def values(self):
         return steps_cyl_table_values(self.handle, self.n_delta, self.n_rho)
+
+    def values_f64(self):
+        return steps_cyl_table_values_f64(self.handle, self.n_delta, self.n_rho)
 
 
 def steps_cyl_forces_table(pos, mass, eps, L, table, order=2, targets=None, out_acc=None,

@@ -115,7 +115,7 @@ __device__ double cylinder_field(double rho, const CompArgs &c) {
     if (rho <= 0.0) return 0.0;
     const double R = c.R, Z = c.Z, Z2 = Z * Z;
     double A = 0.0;
-    for (int i = 0; i < kGL; ++i) {
+    for (int i = 0; i < kGL && Z < INFINITY; ++i) {  // A -> 0 for an infinite cylinder
         const double ct = cos(c.q.x[i]);
         const double t = 2.0 * rho * R * ct;
         const double base = R * R + rho * rho;
@@ -216,16 +216,24 @@ void advance(const Background &bg, double a0, double span, int n_sub, double out
     for (int q = 0; q < 3; ++q) out[q] = y[q];
 }
 
+// the force and compensation settings, common to both ways of giving the factors
+int check_force_params(const steps_cyl_kdk_params *p) {
+    if (p->compensate && (!finite_positive(p->R_cyl) || !std::isfinite(p->rho0) || p->rho0 < 0.0))
+        return fail(STEPS_EINVAL, "compensation needs R_cyl > 0 and rho0 >= 0");
+    if (p->net && p->table) return fail(STEPS_EINVAL, "give a network or a table, not both");
+    if (p->table && p->table_order != 1 && p->table_order != 2)
+        return fail(STEPS_EINVAL, "table_order=%d: 1 (CIC) or 2 (TSC)", p->table_order);
+    if (!p->net && !p->table && (p->n_img < 0 || p->n_img > STEPS_MAX_NIMG))
+        return fail(STEPS_EINVAL, "n_img=%d outside [0, %d]", p->n_img, STEPS_MAX_NIMG);
+    return STEPS_OK;
+}
+
 int check_params(const steps_cyl_kdk_params *p) {
     if (!p) return fail(STEPS_EINVAL, "params must be non-null");
     if (p->factors) {
         for (int q = 0; q < 3; ++q)
             if (!std::isfinite(p->factors[q])) return fail(STEPS_EINVAL, "non-finite step factor");
-        if (p->compensate && (!finite_positive(p->R_cyl) || !std::isfinite(p->rho0) || p->rho0 < 0.0))
-            return fail(STEPS_EINVAL, "compensation needs R_cyl > 0 and rho0 >= 0");
-        if (!p->net && (p->n_img < 0 || p->n_img > STEPS_MAX_NIMG))
-            return fail(STEPS_EINVAL, "n_img=%d outside [0, %d]", p->n_img, STEPS_MAX_NIMG);
-        return STEPS_OK;
+        return check_force_params(p);
     }
     const double v[] = {p->a_begin, p->a_end, p->H0, p->Omega_m, p->Omega_L, p->Omega_r, p->Omega_k, p->w0, p->wa};
     for (double x : v)
@@ -240,11 +248,7 @@ int check_params(const steps_cyl_kdk_params *p) {
         const double H = bg.hubble(a);
         if (!std::isfinite(H) || !(H > 0.0)) return fail(STEPS_EDOMAIN, "H(a) is not positive at a=%g", a);
     }
-    if (p->compensate && (!finite_positive(p->R_cyl) || !std::isfinite(p->rho0) || p->rho0 < 0.0))
-        return fail(STEPS_EINVAL, "compensation needs R_cyl > 0 and rho0 >= 0");
-    if (!p->net && (p->n_img < 0 || p->n_img > STEPS_MAX_NIMG))
-        return fail(STEPS_EINVAL, "n_img=%d outside [0, %d]", p->n_img, STEPS_MAX_NIMG);
-    return STEPS_OK;
+    return check_force_params(p);
 }
 
 void factors(const steps_cyl_kdk_params *p, double out[3]) {
@@ -370,8 +374,8 @@ STEPS_API int steps_cyl_compensation(const double *pos, int64_t N, double R_cyl,
                                      double *out, hipStream_t stream) {
     if (!pos || !out) return fail(STEPS_EINVAL, "pos and out must be non-null");
     if (N < 1 || N > INT32_MAX) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^31-1]", (long long)N);
-    if (!finite_positive(R_cyl) || !finite_positive(Z) || !std::isfinite(rho0) || rho0 < 0.0)
-        return fail(STEPS_EINVAL, "need R_cyl > 0, Z > 0 finite and rho0 >= 0");
+    if (!finite_positive(R_cyl) || !(Z > 0.0) || !std::isfinite(rho0) || rho0 < 0.0)
+        return fail(STEPS_EINVAL, "need R_cyl > 0 finite, Z > 0 (infinity allowed) and rho0 >= 0");
     int rc = require_device();
     if (rc) return rc;
     clear_error();
@@ -393,7 +397,14 @@ STEPS_API int steps_cyl_kdk_step(double *pos, double *mom, const double *mass, c
     clear_error();
     double f[3];
     factors(params, f);
-    const double Z = params->net ? 1024.5 * L : (params->n_img + 0.5) * L;
+    double Z = (params->n_img + 0.5) * L;
+    if (params->net) {
+        Z = 1024.5 * L;
+    } else if (params->table) {
+        int n_far = 0;
+        if ((rc = steps_cyl_table_info(params->table, nullptr, nullptr, nullptr, &n_far))) return rc;
+        Z = n_far < 0 ? INFINITY : (n_far + 0.5) * L;
+    }
     const CompArgs c = comp_args(params->R_cyl, Z, params->rho0);
     const dim3 grid((unsigned)((N + 255) / 256)), block(256);
     hipLaunchKernelGGL(kick_kernel, grid, block, 0, stream, pos, mom, acc_inout, N, f[0], c, params->compensate);
@@ -403,6 +414,9 @@ STEPS_API int steps_cyl_kdk_step(double *pos, double *mom, const double *mass, c
     if (params->net)
         rc = launch_forces_learned(pos, mass, eps, N, L, params->net, nullptr, N, STEPS_SUM_COMPENSATED,
                                    acc_inout, nullptr, stream);
+    else if (params->table)
+        rc = steps_cyl_forces_table(pos, mass, eps, N, L, params->table, params->table_order, nullptr, N,
+                                    acc_inout, nullptr, stream);
     else
         rc = launch_forces_exact(pos, mass, eps, N, L, params->n_img, nullptr, N, STEPS_SUM_COMPENSATED,
                                  acc_inout, nullptr, stream);

@@ -1,22 +1,46 @@
 // Tabulated far-image correction (Sect. 2.2, eq. S1R2EwaldCorrectionTable):
-// the image band 2 <= |n| <= n_far of one unit mass on an equally spaced
-// grid in delta = |d|/L in [0, 1/2] and r = rho/L in [0, r_max], with one
-// ghost node beyond every edge, interpolated with cloud-in-cell (bilinear)
-// or triangular-shaped-cloud (quadratic B-spline, 3 x 3 nodes) weights and
+// the image band of one unit mass on an equally spaced grid in
+// delta = |d|/L in [0, 1/2] and r = rho/L in [0, r_max], with one ghost node
+// beyond every edge, interpolated with cloud-in-cell (bilinear) or
+// triangular-shaped-cloud (quadratic B-spline, 3 x 3 nodes) weights and
 // added to the exact images |n| <= 1.
 //
-// The nodes are built on the GPU in FP64 and stored as FP32 pairs
-// (T_z, T_rho) in device memory; at 146 x 131 nodes (the paper's 144 x 128
-// grid plus ghosts) the table is 153 KB and stays in L2.  The force kernel
-// maps one target per thread like the exact kernel; sources come through LDS
-// tiles, the table through the vector caches.  Pairs beyond r_max take the
-// exact band, shared by the 64 lanes of the wave.
+// Two kinds of table:
+//  * band: the images 2 <= |n| <= n_far, summed directly in FP64;
+//  * complete: every image |n| >= 2 (N_cut -> infinity), from the Ewald split
+//    of Sect. 2.2 (eqs. cylindricalEwaldSplit, EwaldRealSum, EwaldRecSum):
+//    a real-space sum over n = -n_max..n_max weighted by
+//    Q(3/2, alpha^2 r^2) = erfc(alpha r) + 2 alpha r exp(-alpha^2 r^2)/sqrt(pi),
+//    Fourier modes m = 1..m_max, and the m = 0 mode
+//    -2 (1 - exp(-alpha^2 rho^2)) / rho.  The Fourier kernel is either the
+//    incomplete Bessel function
+//        B(k, rho) = int_{1/(4 alpha^2)}^inf exp(-k^2 t - rho^2/(4 t)) dt/(2 t)
+//    that Poisson summation of the smooth part gives for one periodic
+//    direction (force (4/L) grad[cos(k d) B]), or, for comparison, the kernel
+//    as printed in eq. Bkernel with its printed prefactor (-(2/L)), which
+//    only matches the complete sum where its modes are negligible.  The
+//    three nearest images enter the real-space sum as (Ewald - Newton),
+//    -P(3/2, alpha^2 r^2), so the node values carry no cancellation.
+//    Pairs beyond r_max use the line-mass limit of the complete sum,
+//    F = (0, -2/rho) per G m / L, minus the three nearest images: the
+//    modes decay as exp(-2 pi rho/L), below 1e-10 for rho_max >= 4 L.
+//
+// The nodes are built on the GPU in FP64, one wave per node (the image or
+// mode range split over the lanes, then a fixed-order reduction), kept in
+// FP64 for inspection and stored as FP32 pairs (T_z, T_rho) for the force
+// kernel; at 146 x 131 nodes (the paper's 144 x 128 grid plus ghosts) the
+// FP32 table is 153 KB and stays in L2.  The force kernel maps one target
+// per thread like the exact kernel; sources come through LDS tiles, the
+// table through the vector caches.  Pairs of a band table beyond r_max take
+// the exact band, shared by the 64 lanes of the wave.
 #include "common.h"
 #include "pair_fp32.h"
 
 struct steps_cyl_table {
-    float2 *nodes = nullptr;  // [(n_r + 3) * (n_d + 3)], node (i, j) at (j + 1) * (n_d + 3) + i + 1
+    float2 *nodes = nullptr;     // [(n_r + 3) * (n_d + 3)], node (i, j) at (j + 1) * (n_d + 3) + i + 1
+    double2 *nodes64 = nullptr;  // the same nodes in FP64
     int n_d = 0, n_r = 0, n_far = 0;
+    int complete = 0;            // 1: every image |n| >= 2 (Ewald build)
     double r_max = 0.0;
 };
 
@@ -33,21 +57,153 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
     return y * (1.5 - 0.5 * x * y * y);
 }
 
-__global__ void build_kernel(float2 *nodes, int n_d, int n_r, double h_d, double h_r, int n_far) {
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ void store_node(float2 *nodes, double2 *nodes64, int k, double tz, double tr) {
+    if ((threadIdx.x & 63) == 0) {
+        nodes64[k] = make_double2(tz, tr);
+        nodes[k] = make_float2((float)tz, (float)tr);
+    }
+}
+
+// band 2 <= |n| <= n_far, one wave per node; each lane sums its images from
+// the far end inwards (smallest terms first)
+__global__ __launch_bounds__(64) void build_band_kernel(float2 *nodes, double2 *nodes64, int n_d, double h_d,
+                                                        double h_r, int n_far) {
     const int w = n_d + 3;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= w * (n_r + 3)) return;
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
     const int i = k % w - 1, j = k / w - 1;
     const double delta = i * h_d, r = j * h_r, r2 = r * r;
     double tz = 0.0, tr = 0.0;
-    for (int q = n_far; q >= 2; --q) {  // smallest terms first
+    for (int q = n_far - lane; q >= 2; q -= 64) {
         const double up = delta - (double)q, um = delta + (double)q;
         const double ip = rsqrt_f64(up * up + r2), im = rsqrt_f64(um * um + r2);
         const double ip3 = ip * ip * ip, im3 = im * im * im;
         tz += -up * ip3 - um * im3;
         tr += -r * (ip3 + im3);
     }
-    nodes[k] = make_float2((float)tz, (float)tr);
+    store_node(nodes, nodes64, k, wave_sum(tz), wave_sum(tr));
+}
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoOverSqrtPi = 1.12837916709551257390;
+
+// P(3/2, x^2) = erf(x) - 2 x exp(-x^2)/sqrt(pi): by its power series
+// x^3 exp(-x^2)/Gamma(5/2) * sum_j x^2j / ((5/2)(7/2)...(3/2+j)) for x < 1
+// (all terms positive), directly beyond
+__device__ double gamma_p32(double x) {
+    const double y = x * x;
+    if (x < 1.0) {
+        double term = 1.0, sum = 1.0;
+        for (int j = 1; j < 40; ++j) {
+            term *= y / (1.5 + j);
+            sum += term;
+            if (term < 1e-17 * sum) break;
+        }
+        return x * y * exp(-y) * sum / (0.75 * 1.77245385090551602730);
+    }
+    return erf(x) - kTwoOverSqrtPi * x * exp(-y);
+}
+
+// (B, dB/drho) of the incomplete-Bessel kernel.  With s = ln(4 alpha^2 t),
+// c = k^2/(4 alpha^2) and b = alpha^2 rho^2:
+//   B = 1/2 int_0^inf exp(-c e^s - b e^-s) ds,
+//   dB/drho = -alpha^2 rho int_0^inf exp(-c e^s - b e^-s - s) ds.
+// The exponent has its minimum E0 at s0 = max(0, ln(b/c)/2); the integral is
+// taken where it stays below E0 + 45, by 8-point Gauss-Legendre on panels of
+// width at most 1/16 (the integrand is analytic and varies on the scale
+// 1/(c e^s + b e^-s) there).
+__device__ void kernel_bessel(double k, double rho, double alpha, double &B, double &dB) {
+    const double c = k * k / (4.0 * alpha * alpha), b = alpha * alpha * rho * rho;
+    const double s0 = (b > c) ? 0.5 * log(b / c) : 0.0;
+    const double E0 = c * exp(s0) + b * exp(-s0);
+    B = 0.0;
+    dB = 0.0;
+    if (E0 > 700.0) return;
+    const double s_hi = log((E0 + 45.0) / c);
+    const double s_lo = (b > E0 + 45.0) ? log(b / (E0 + 45.0)) : 0.0;
+    const int panels = max(1, (int)ceil((s_hi - s_lo) * 16.0));
+    const double hw = 0.5 * (s_hi - s_lo) / panels;
+    // Gauss-Legendre, 8 points on [-1, 1] (symmetric pairs)
+    const double gx[4] = {0.18343464249564980494, 0.52553240991632898582, 0.79666647741362673959,
+                          0.96028985649753623168};
+    const double gw[4] = {0.36268378337836198297, 0.31370664587788728734, 0.22238103445337447054,
+                          0.10122853629037625915};
+    double sb = 0.0, sd = 0.0;
+    for (int p = 0; p < panels; ++p) {
+        const double mid = s_lo + (2 * p + 1) * hw;
+        for (int q = 0; q < 4; ++q) {
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const double s = mid + sgn * hw * gx[q];
+                const double es = exp(s);
+                const double f = gw[q] * exp(-c * es - b / es);
+                sb += f;
+                sd += f / es;
+            }
+        }
+    }
+    B = 0.5 * hw * sb;
+    dB = -alpha * alpha * rho * hw * sd;
+}
+
+// (B_p, dB_p/drho) of the printed kernel; exp(k rho) erfc(a+) written as
+// exp(-k^2/(4 alpha^2) - alpha^2 rho^2) erfcx(a+) so that nothing overflows,
+// and the Gaussian terms of the two derivatives cancel
+__device__ void kernel_printed(double k, double rho, double alpha, double &B, double &dB) {
+    const double ap = k / (2.0 * alpha) + alpha * rho, am = k / (2.0 * alpha) - alpha * rho;
+    const double t1 = exp(-k * k / (4.0 * alpha * alpha) - alpha * alpha * rho * rho) * erfcx(ap);
+    const double t2 = exp(-k * rho) * erfc(am);
+    B = t1 + t2;
+    dB = k * (t1 - t2);
+}
+
+// complete band (every |n| >= 2) at (delta, |r|) by the Ewald split, one wave
+// per node: lane l takes the real-space images n = -n_max + l + 64 t and the
+// modes m = 1 + l + 64 t
+__global__ __launch_bounds__(64) void build_ewald_kernel(float2 *nodes, double2 *nodes64, int n_d, double h_d,
+                                                         double h_r, double alpha, int n_max, int m_max,
+                                                         int printed) {
+    const int w = n_d + 3;
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int i = k % w - 1, j = k / w - 1;
+    const double delta = i * h_d, rs = j * h_r, r = fabs(rs), r2 = r * r;
+    double tz = 0.0, tr = 0.0;
+    for (int n = -n_max + lane; n <= n_max; n += 64) {
+        const double u = delta - (double)n;
+        const double q2 = u * u + r2;
+        if (q2 == 0.0) continue;  // the subtracted n = 0 term tends to zero with s_n
+        const double q = sqrt(q2), x = alpha * q;
+        const double p = gamma_p32(x);
+        // |n| >= 2: Q = 1 - P; |n| <= 1: Q - 1 = -P (Newton's term removed)
+        const double wgt = (n >= -1 && n <= 1) ? -p : erfc(x) + kTwoOverSqrtPi * x * exp(-x * x);
+        const double inv3 = 1.0 / (q2 * q);
+        tz -= u * inv3 * wgt;
+        tr -= r * inv3 * wgt;
+    }
+    for (int m = 1 + lane; m <= m_max; m += 64) {
+        const double km = 2.0 * kPi * m;
+        double B, dB, pre;
+        if (printed) {
+            kernel_printed(km, r, alpha, B, dB);
+            pre = -2.0;
+        } else {
+            kernel_bessel(km, r, alpha, B, dB);
+            pre = 4.0;
+        }
+        double sn, cs;
+        sincos(km * delta, &sn, &cs);
+        tz += pre * (-km * sn) * B;
+        tr += pre * cs * dB;
+    }
+    tz = wave_sum(tz);
+    tr = wave_sum(tr);
+    if (r > 0.0) tr += 2.0 * expm1(-alpha * alpha * r2) / r;  // m = 0
+    store_node(nodes, nodes64, k, tz, rs < 0.0 ? -tr : tr);
 }
 
 struct TableArgs {
@@ -58,7 +214,7 @@ struct TableArgs {
     double L, invL, halfL;
     float invLf, invL2f, inv_hd, inv_hr, r_max;
     ImageConsts c;  // n_img = 1
-    int N, n_tgt, n_d, n_r, n_far, w;
+    int N, n_tgt, n_d, n_r, n_far, w, complete;
 };
 
 // exact band of one pair shared by the wave (see the learned kernel)
@@ -187,7 +343,24 @@ __global__ __launch_bounds__(kBlock) void forces_table_kernel(TableArgs a) {
                     Rz = 0.f;
                     Rr = 0.f;
                 }
-                uint64_t outside = __ballot(!inside && !self && active);
+                if (a.complete) {
+                    // line-mass limit of the complete sum minus the three nearest images
+                    if (!inside && !self) {
+                        const float ds = d * a.invLf, r2 = r * r;
+                        float nz = 0.f, nr = 0.f;
+#pragma unroll
+                        for (int n = -1; n <= 1; ++n) {
+                            const float u = ds - (float)n;
+                            const float iq = __builtin_amdgcn_rsqf(__builtin_fmaf(u, u, r2));
+                            const float iq3 = iq * iq * iq;
+                            nz = __builtin_fmaf(-u, iq3, nz);
+                            nr = __builtin_fmaf(-r, iq3, nr);
+                        }
+                        Rz = -nz;
+                        Rr = -2.f * __builtin_amdgcn_rcpf(r) - nr;
+                    }
+                }
+                uint64_t outside = a.complete ? 0 : __ballot(!inside && !self && active);
                 while (outside) {
                     const int c = __builtin_ctzll(outside);
                     outside &= outside - 1;
@@ -234,43 +407,91 @@ hipError_t launch_t(const TableArgs &a, hipStream_t stream) {
 
 using namespace steps;
 
-STEPS_API int steps_cyl_table_create(int n_delta, int n_rho, double rho_max, int n_far, hipStream_t stream,
-                                     steps_cyl_table **out) {
-    if (!out) return fail(STEPS_EINVAL, "out must be non-null");
-    if (n_delta < 2 || n_delta > 4096 || n_rho < 2 || n_rho > 4096)
-        return fail(STEPS_EINVAL, "grid sizes must lie in [2, 4096]");
-    if (!finite_positive(rho_max) || rho_max > 1e4) return fail(STEPS_EINVAL, "rho_max must be finite and > 0");
-    if (n_far < 2 || n_far > (1 << 20)) return fail(STEPS_EINVAL, "n_far=%d outside [2, 2^20]", n_far);
-    int rc = require_device();
-    if (rc) return rc;
-    clear_error();
+namespace {
+
+steps_cyl_table *new_table(int n_delta, int n_rho, double rho_max, int n_far, int complete) {
     steps_cyl_table *t = new (std::nothrow) steps_cyl_table();
-    if (!t) return fail(STEPS_ENOMEM, "out of host memory");
+    if (!t) return nullptr;
     t->n_d = n_delta;
     t->n_r = n_rho;
     t->r_max = rho_max;
     t->n_far = n_far;
-    const int nodes = (n_delta + 3) * (n_rho + 3);
+    t->complete = complete;
+    const size_t nodes = (size_t)(n_delta + 3) * (n_rho + 3);
     if (hipMalloc(&t->nodes, nodes * sizeof(float2)) != hipSuccess) {
         delete t;
-        return fail(STEPS_ENOMEM, "table allocation failed");
+        return nullptr;
     }
-    hipLaunchKernelGGL(build_kernel, dim3((nodes + 255) / 256), dim3(256), 0, stream, t->nodes, n_delta, n_rho,
-                       0.5 / n_delta, rho_max / n_rho, n_far);
+    if (hipMalloc(&t->nodes64, nodes * sizeof(double2)) != hipSuccess) {
+        (void)hipFree(t->nodes);
+        delete t;
+        return nullptr;
+    }
+    return t;
+}
+
+int finish_build(steps_cyl_table *t, hipStream_t stream, steps_cyl_table **out) {
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
-        (void)hipFree(t->nodes);
-        delete t;
+        steps_cyl_table_destroy(t);
         return hip_status(e, "table build");
     }
     *out = t;
     return STEPS_OK;
 }
 
+int check_grid(int n_delta, int n_rho, double rho_max) {
+    if (n_delta < 2 || n_delta > 4096 || n_rho < 2 || n_rho > 4096)
+        return fail(STEPS_EINVAL, "grid sizes must lie in [2, 4096]");
+    if (!finite_positive(rho_max) || rho_max > 1e4) return fail(STEPS_EINVAL, "rho_max must be finite and > 0");
+    return STEPS_OK;
+}
+
+}  // namespace
+
+STEPS_API int steps_cyl_table_create(int n_delta, int n_rho, double rho_max, int n_far, hipStream_t stream,
+                                     steps_cyl_table **out) {
+    if (!out) return fail(STEPS_EINVAL, "out must be non-null");
+    int rc = check_grid(n_delta, n_rho, rho_max);
+    if (rc) return rc;
+    if (n_far < 2 || n_far > STEPS_TABLE_MAX_FAR)
+        return fail(STEPS_EINVAL, "n_far=%d outside [2, %d]", n_far, STEPS_TABLE_MAX_FAR);
+    if ((rc = require_device())) return rc;
+    clear_error();
+    steps_cyl_table *t = new_table(n_delta, n_rho, rho_max, n_far, 0);
+    if (!t) return fail(STEPS_ENOMEM, "table allocation failed");
+    const int nodes = (n_delta + 3) * (n_rho + 3);
+    hipLaunchKernelGGL(build_band_kernel, dim3(nodes), dim3(64), 0, stream, t->nodes, t->nodes64, n_delta,
+                       0.5 / n_delta, rho_max / n_rho, n_far);
+    return finish_build(t, stream, out);
+}
+
+STEPS_API int steps_cyl_table_create_ewald(int n_delta, int n_rho, double rho_max, double alpha, int n_max,
+                                           int m_max, int kernel, hipStream_t stream, steps_cyl_table **out) {
+    if (!out) return fail(STEPS_EINVAL, "out must be non-null");
+    int rc = check_grid(n_delta, n_rho, rho_max);
+    if (rc) return rc;
+    if (rho_max < 4.0) return fail(STEPS_EINVAL, "a complete table needs rho_max >= 4 (got %g)", rho_max);
+    if (!finite_positive(alpha) || alpha > 64.0) return fail(STEPS_EINVAL, "alpha must lie in (0, 64]");
+    if (n_max < 1 || n_max > 1024) return fail(STEPS_EINVAL, "n_max=%d outside [1, 1024]", n_max);
+    if (m_max < 0 || m_max > 1024) return fail(STEPS_EINVAL, "m_max=%d outside [0, 1024]", m_max);
+    if (kernel != STEPS_EWALD_BESSEL && kernel != STEPS_EWALD_PRINTED)
+        return fail(STEPS_EINVAL, "kernel=%d: STEPS_EWALD_BESSEL or STEPS_EWALD_PRINTED", kernel);
+    if ((rc = require_device())) return rc;
+    clear_error();
+    steps_cyl_table *t = new_table(n_delta, n_rho, rho_max, 0, 1);
+    if (!t) return fail(STEPS_ENOMEM, "table allocation failed");
+    const int nodes = (n_delta + 3) * (n_rho + 3);
+    hipLaunchKernelGGL(build_ewald_kernel, dim3(nodes), dim3(64), 0, stream, t->nodes, t->nodes64, n_delta,
+                       0.5 / n_delta, rho_max / n_rho, alpha, n_max, m_max, kernel == STEPS_EWALD_PRINTED);
+    return finish_build(t, stream, out);
+}
+
 STEPS_API void steps_cyl_table_destroy(steps_cyl_table *t) {
     if (!t) return;
     (void)hipFree(t->nodes);
+    (void)hipFree(t->nodes64);
     delete t;
 }
 
@@ -279,6 +500,25 @@ STEPS_API int steps_cyl_table_values(const steps_cyl_table *t, float *host_out) 
     clear_error();
     const size_t nodes = (size_t)(t->n_d + 3) * (t->n_r + 3);
     STEPS_CHECK_HIP(hipMemcpy(host_out, t->nodes, nodes * sizeof(float2), hipMemcpyDeviceToHost));
+    return STEPS_OK;
+}
+
+STEPS_API int steps_cyl_table_values_f64(const steps_cyl_table *t, double *host_out) {
+    if (!t || !host_out) return fail(STEPS_EINVAL, "table and host_out must be non-null");
+    clear_error();
+    const size_t nodes = (size_t)(t->n_d + 3) * (t->n_r + 3);
+    STEPS_CHECK_HIP(hipMemcpy(host_out, t->nodes64, nodes * sizeof(double2), hipMemcpyDeviceToHost));
+    return STEPS_OK;
+}
+
+STEPS_API int steps_cyl_table_info(const steps_cyl_table *t, int *n_delta, int *n_rho, double *rho_max,
+                                   int *n_far) {
+    if (!t) return fail(STEPS_EINVAL, "table must be non-null");
+    clear_error();
+    if (n_delta) *n_delta = t->n_d;
+    if (n_rho) *n_rho = t->n_r;
+    if (rho_max) *rho_max = t->r_max;
+    if (n_far) *n_far = t->complete ? -1 : t->n_far;
     return STEPS_OK;
 }
 
@@ -324,6 +564,7 @@ STEPS_API int steps_cyl_forces_table(const double *pos, const double *mass, cons
     a.n_d = t->n_d;
     a.n_r = t->n_r;
     a.n_far = t->n_far;
+    a.complete = t->complete;
     a.w = t->n_d + 3;
     hipError_t e;
     if (order == 1)

@@ -182,3 +182,39 @@ def test_mlp_calls_reject_null_handles():
     assert L.steps_cyl_mlp_save(None, b"/tmp/x") == sc.STEPS_EINVAL
     assert L.steps_cyl_mlp_samples(None, 4, P, P, None) == sc.STEPS_EINVAL
     L.steps_cyl_mlp_destroy(None)
+
+
+@pytest.mark.parametrize("args", [
+    (1, 8, 6.4, 1024), (8, 5000, 6.4, 1024), (8, 8, 0.0, 1024), (8, 8, float("nan"), 1024),
+    (8, 8, 6.4, 1), (8, 8, 6.4, (1 << 24) + 1),
+])
+def test_table_create_rejects_bad_arguments(args):
+    h = ctypes.c_void_p()
+    assert sc.lib().steps_cyl_table_create(*args, None, ctypes.byref(h)) == sc.STEPS_EINVAL
+    assert sc.lib().steps_cyl_table_create(8, 8, 6.4, 1024, None, None) == sc.STEPS_EINVAL
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((8, 8, 3.9, 2.0, 5, 12, 0), "rho_max >= 4"),
+    ((8, 8, 6.4, 0.0, 5, 12, 0), "alpha"),
+    ((8, 8, 6.4, 65.0, 5, 12, 0), "alpha"),
+    ((8, 8, 6.4, 2.0, 0, 12, 0), "n_max"),
+    ((8, 8, 6.4, 2.0, 5, -1, 0), "m_max"),
+    ((8, 8, 6.4, 2.0, 5, 2000, 0), "m_max"),
+    ((8, 8, 6.4, 2.0, 5, 12, 2), "kernel"),
+    ((1, 8, 6.4, 2.0, 5, 12, 0), "grid"),
+])
+def test_ewald_table_create_rejects_bad_arguments(args, msg):
+    h = ctypes.c_void_p()
+    assert sc.lib().steps_cyl_table_create_ewald(*args, None, ctypes.byref(h)) == sc.STEPS_EINVAL
+    assert msg in sc.steps_cyl_last_error()
+
+
+def test_table_calls_reject_null_handles():
+    L = sc.lib()
+    P = ctypes.c_void_p(64)
+    assert L.steps_cyl_table_values(None, P) == sc.STEPS_EINVAL
+    assert L.steps_cyl_table_values_f64(None, P) == sc.STEPS_EINVAL
+    assert L.steps_cyl_table_info(None, None, None, None, None) == sc.STEPS_EINVAL
+    assert L.steps_cyl_forces_table(P, P, P, 10, 1.0, None, 1, None, 10, P, None, None) == sc.STEPS_EINVAL
+    L.steps_cyl_table_destroy(None)

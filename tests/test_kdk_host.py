@@ -102,3 +102,17 @@ def test_explicit_factors_pass_through():
     with pytest.raises(sc.StepsError) as e:
         sc.steps_cyl_kdk_factors(bad)
     assert e.value.code == sc.STEPS_EINVAL
+
+
+def test_table_settings_are_checked():
+    # a table handle is not dereferenced by the checks (host only)
+    fake = 0x1000
+    base = dict(a_begin=0.1, a_end=0.2, H0=1.0, Omega_m=0.3, Omega_L=0.7)
+    with pytest.raises(sc.StepsError) as e:
+        sc.steps_cyl_kdk_factors(sc.kdk_params(**base, table=fake, table_order=3))
+    assert e.value.code == sc.STEPS_EINVAL and "table_order" in str(e.value)
+    with pytest.raises(sc.StepsError) as e:
+        sc.steps_cyl_kdk_factors(sc.kdk_params(**base, table=fake, net=fake))
+    assert e.value.code == sc.STEPS_EINVAL
+    # with a table n_img is not used
+    sc.steps_cyl_kdk_factors(sc.kdk_params(**base, table=fake, table_order=1, n_img=-5))

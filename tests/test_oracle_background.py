@@ -88,6 +88,15 @@ def test_cylinder_field_infinite_limit_outside():
                                                                  rel=1e-9)
 
 
+@pytest.mark.parametrize("rho", [0.2, 2.5, 3.157, 4.0])
+def test_cylinder_field_of_infinite_cylinder_is_gauss_law(rho):
+    # eq. F_horiz_infty inside; Gauss's law for an infinite line of mass outside
+    R, rho0 = 3.157, 0.0319
+    f = bg.cylinder_field(rho, R, math.inf, rho0)
+    ref = -2 * math.pi * rho0 * (rho if rho <= R else R * R / rho)
+    assert f == pytest.approx(ref, rel=1e-10)
+
+
 def test_printed_formula_has_wrong_limit():
     # the finite-height expression as printed tends to +pi G rho0 rho: the
     # reading documented in the oracle (opposite sign, half the B term)
