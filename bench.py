@@ -212,8 +212,26 @@ def learned_leg(args, dev):
                   file=sys.stderr, flush=True)
         return total
 
+    table = sc.CorrectionTable(128, 144, 6.4, 1024)
+    acc_t = {1: torch.empty((3, N), dtype=torch.float32, device=dev),
+             2: torch.empty((3, N), dtype=torch.float32, device=dev)}
+
+    def run_table(order):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sc.steps_cyl_forces_table(pos, m, e, p.L, table, order=order, potential=False,
+                                  out_acc=acc_t[order], stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        print(f"[bench] table order {order} N={N} done ({ms / 1e3:.1f} s)", file=sys.stderr, flush=True)
+        return ms
+
     sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=idx[0][:1024], potential=False)
+    sc.steps_cyl_forces_table(pos, m, e, p.L, table, order=1, targets=idx[0][:1024], potential=False)
     torch.cuda.synchronize()
+    ms_t = {o: run_table(o) for o in (1, 2)}
     ms_l = run("learned")
     ms_x = run("exact")
     t = torch.from_numpy(synth.target_sample(N, 1024, seed=7)).to(dev)
@@ -228,11 +246,14 @@ def learned_leg(args, dev):
         return float(f"{v.max():.3e}"), float(f"{np.median(v):.3e}")
 
     el, ex, e8 = err(acc_l[:, t]), err(acc_x[:, t]), err(a8)
+    et = {o: err(acc_t[o][:, t]) for o in (1, 2)}
     pairs = float(N) * N
     net.close()
+    table.close()
     return {
         "N": N, "workload": f"stereographic cylinder load N={N} (seed 0): exact |n|<=1 + "
-                            "network correction for 2<=|n|<=1024 vs exact |n|<=1024",
+                            "network (or 144x128 table) correction for 2<=|n|<=1024 "
+                            "vs exact |n|<=1024",
         "ms_learned": round(ms_l, 1), "ms_exact1024": round(ms_x, 1),
         "learned_G_pairs_per_s": round(pairs / (ms_l * 1e-3) / 1e9, 3),
         "exact1024_G_pairs_per_s": round(pairs / (ms_x * 1e-3) / 1e9, 3),
@@ -240,6 +261,13 @@ def learned_leg(args, dev):
         "err_vs_f64_exact1024_targets": 1024,
         "learned_max_rel_err": el[0], "learned_median_rel_err": el[1],
         "exact1024_fp32_max_rel_err": ex[0], "exact8_max_rel_err": e8[0],
+        "table_144x128": {
+            "cic_ms": round(ms_t[1], 1), "tsc_ms": round(ms_t[2], 1),
+            "cic_G_pairs_per_s": round(pairs / (ms_t[1] * 1e-3) / 1e9, 2),
+            "tsc_G_pairs_per_s": round(pairs / (ms_t[2] * 1e-3) / 1e9, 2),
+            "cic_max_rel_err": et[1][0], "cic_median_rel_err": et[1][1],
+            "tsc_max_rel_err": et[2][0], "tsc_median_rel_err": et[2][1],
+        },
     }
 
 

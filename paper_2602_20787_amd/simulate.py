@@ -4,11 +4,14 @@ The initial load is the stereographic cylinder load with Gaussian
 displacements (rms half the mean inter-particle spacing), zero momenta, flat
 LCDM (Omega_m = 0.3, Omega_L = 0.7) with H0 fixed by the load's comoving
 density (H0^2 = 8 pi G rho0 / (3 Omega_m)), and steps uniform in ln a.  Forces
-are the learned correction (exact |n| <= 1 + network) or the exact sum with
-|n| <= n_img; the homogeneous-cylinder pull is compensated.  Every
---check-every steps the axial momentum and the force error on sampled targets
-against the FP64 GPU reference with |n| <= 1024 (learned mode) or n_img
-(exact mode) are reported.  Prints one line per step and a JSON summary.
+are the learned correction (exact |n| <= 1 + network), the exact sum with
+|n| <= n_img, the interpolated table of the band 2 <= |n| <= 1024 (Sect. 2.2)
+or the complete table of every image (N_cut -> infinity, from the Ewald
+split); the homogeneous-cylinder pull of the matching height is compensated.
+Every --check-every steps the axial momentum and the force error on sampled
+targets against the FP64 GPU reference (|n| <= 1024 for the learned and band
+modes, n_img for exact, 4096 for complete) are reported.  Prints one line
+per step and a JSON summary.
 
     python -m paper_2602_20787_amd.simulate --N 131072 --steps 64
 """
@@ -34,7 +37,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--a0", type=float, default=0.02)
     ap.add_argument("--a1", type=float, default=1.0)
-    ap.add_argument("--mode", choices=["learned", "exact"], default="learned")
+    ap.add_argument("--mode", choices=["learned", "exact", "table", "complete"], default="learned")
+    ap.add_argument("--table-order", type=int, choices=[1, 2], default=2)
     ap.add_argument("--n-img", type=int, default=8)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--check-targets", type=int, default=4096)
@@ -60,11 +64,18 @@ def main(argv=None):
     e = torch.from_numpy(p.eps).to(dev)
     mom = torch.zeros_like(pos)
     net = sc.Mlp.load(args.net) if args.mode == "learned" else None
-    truth_img = 1024 if net is not None else args.n_img
+    table = None
+    if args.mode == "table":
+        table = sc.CorrectionTable(128, 144, 6.4, 1024)
+    elif args.mode == "complete":
+        table = sc.CorrectionTable.ewald(128, 144, 6.4, 2.0, 5, 12)
+    truth_img = {"learned": 1024, "table": 1024, "complete": 4096}.get(args.mode, args.n_img)
 
     def forces():
         if net is not None:
             a, _ = sc.steps_cyl_forces_learned(pos, m, e, L, net, potential=False)
+        elif table is not None:
+            a, _ = sc.steps_cyl_forces_table(pos, m, e, L, table, order=args.table_order, potential=False)
         else:
             a, _ = sc.steps_cyl_forces(pos, m, e, L, args.n_img, potential=False)
         return a
@@ -92,7 +103,7 @@ def main(argv=None):
     pz_max_ratio = 0.0
     for k in range(args.steps):
         par = sc.kdk_params(grid[k], grid[k + 1], H0, Om, OL, R_cyl=R, rho0=rho0,
-                            n_img=args.n_img, net=net)
+                            n_img=args.n_img, net=net, table=table, table_order=args.table_order)
         sc.steps_cyl_kdk_step(pos, mom, m, e, L, par, acc)
         torch.cuda.synchronize()
         P, Ps = pz()
@@ -118,6 +129,8 @@ def main(argv=None):
     print(json.dumps(summary), flush=True)
     if net is not None:
         net.close()
+    if table is not None:
+        table.close()
     return 0
 
 

