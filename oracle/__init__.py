@@ -51,6 +51,9 @@ def _load():
         lib.oracle_image_band.argtypes = [dp, dp, ctypes.c_int64, ctypes.c_double,
                                           ctypes.c_int, ctypes.c_int, dp, dp, dp]
         lib.oracle_image_band.restype = ctypes.c_int
+        lib.oracle_pairs.argtypes = [dp, dp, dp, dp, lp, ctypes.c_int64, dp, dp, dp, dp, dp, lp,
+                                     ctypes.c_int64, ctypes.c_double, ctypes.c_int, dp]
+        lib.oracle_pairs.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         for name in ("oracle_spline_force", "oracle_spline_potential"):
@@ -123,6 +126,28 @@ def forces(pos, mass, eps, L, n_img, targets=None, window=0, potential=True):
     if rc != 0:
         raise ValueError("oracle_forces rejected its arguments")
     return acc.reshape(3, T), pot
+
+
+def pairs(tpos, th, tid, spos, sm, sh, sid, L, n_img, acc=None):
+    """Accelerations (3, T) of targets ``tpos`` (3, T) with softening ``th``
+    and ids ``tid`` from sources ``spos`` (3, S), masses ``sm``, softening
+    ``sh`` and ids ``sid``: spline-softened images |n| <= n_img about the
+    minimum image, pairs with equal ids skipped; added into ``acc`` if given."""
+    lib = _load()
+    f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
+    tx, ty, tz = (f64(tpos[k]) for k in range(3))
+    sx, sy, sz = (f64(spos[k]) for k in range(3))
+    th, sm, sh, tid, sid = f64(th), f64(sm), f64(sh), i64(tid), i64(sid)
+    T, S = tx.shape[0], sx.shape[0]
+    out = np.zeros(3 * T) if acc is None else np.ascontiguousarray(acc, dtype=np.float64).reshape(-1).copy()
+    lp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    rc = lib.oracle_pairs(_dptr(tx), _dptr(ty), _dptr(tz), _dptr(th), lp(tid), T,
+                          _dptr(sx), _dptr(sy), _dptr(sz), _dptr(sm), _dptr(sh), lp(sid), S,
+                          float(L), int(n_img), _dptr(out))
+    if rc != 0:
+        raise ValueError("oracle_pairs rejected its arguments")
+    return out.reshape(3, T)
 
 
 def image_band(d, rho, L, n_lo, n_hi):

@@ -163,6 +163,34 @@ int oracle_forces(const double *x, const double *y, const double *z,
  * This is the per-pair quantity of eq. (ForceCylindrical) restricted to a
  * band of images; with n_lo = 2 it is the far-image remainder.
  */
+/* The pair sum of eq. ForceCylindrical for arbitrary lists: targets t
+ * (positions, softening, id) against sources s (positions, mass, softening,
+ * id), images |n| <= n_img about the minimum image, pairs with equal ids
+ * skipped.  acc is [3][n_t] (accumulated into, not cleared). */
+int oracle_pairs(const double *tx, const double *ty, const double *tz, const double *th,
+                 const int64_t *tid, int64_t n_t,
+                 const double *sx, const double *sy, const double *sz, const double *sm,
+                 const double *sh, const int64_t *sid, int64_t n_s, double L, int n_img,
+                 double *acc)
+{
+    if (n_t < 0 || n_s < 0 || !(L > 0.0) || n_img < 0) return -1;
+    for (int64_t k = 0; k < n_t; ++k) {
+        double a[3] = {0.0, 0.0, 0.0};
+        double p = 0.0;
+        double zi = oracle_wrap_position(tz[k], L);
+        for (int64_t j = 0; j < n_s; ++j) {
+            if (tid[k] == sid[j]) continue;
+            double d = oracle_min_image(zi - oracle_wrap_position(sz[j], L), L);
+            for (int n = -n_img; n <= n_img; ++n)
+                add_image(tx[k] - sx[j], ty[k] - sy[j], d - n * L, th[k] + sh[j], sm[j], a, &p);
+        }
+        acc[k] += a[0];
+        acc[n_t + k] += a[1];
+        acc[2 * n_t + k] += a[2];
+    }
+    return 0;
+}
+
 int oracle_image_band(const double *d, const double *rho, int64_t n, double L,
                       int n_lo, int n_hi, double *Fz, double *Frho, double *Pot)
 {

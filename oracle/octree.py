@@ -1,0 +1,241 @@
+"""FP64 oracle of the Barnes-Hut octree force in the S1 x R2 topology.
+
+TEST INFRASTRUCTURE (see the package docstring).
+
+The paper's octree (Sect. 2.4, "Octree"): cubic cells, a root cell twice the
+largest linear size of the volume (the cylinder's height or diameter),
+random shifts of the domain along the axis and rotations about it at every
+step, and a radial correction table measured on the initial load with the
+same tree parameters and subtracted from the tree forces.  What the paper
+leaves open is fixed here (each is a reading):
+
+* Frame.  Positions are rotated by ``angle`` about the axis and shifted by
+  ``shift`` along it (z wrapped into [0, L)); the root cube has side
+  S0 = 2 max(L, 2 R_dom) and centre (0, 0, L/2).  Accelerations are rotated
+  back at the end.
+* Cells.  Integer cell coordinates q = floor((p - lo) 2^21 / S0), clamped to
+  [0, 2^21 - 1], interleaved into a 63-bit Morton key (x bit above y bit
+  above z bit per level).  A cell is split into its octants when it holds
+  more than ``leaf_size`` particles and is above level 21.  The cells form
+  a list in depth-first order (children by octant) with, for each cell, the
+  index of the first cell after its subtree ("skip").
+* Monopoles.  A cell acts through its mass at its centre of mass.
+* Groups.  Targets are taken in key order (ties by index) in groups of
+  ``group`` consecutive particles; a group walks the tree together and
+  accepts a cell when S0/2^level < theta * d and d > h_group + h_cell, with
+  d the periodic (minimum over the images z_c, z_c +- L) distance from the
+  cell's centre of mass to the group's bounding box, h_group and h_cell the
+  largest softening lengths.  Group size 1 is the classical per-particle
+  criterion.  An accepted cell adds its monopole to every target of the
+  group, an opened leaf its particles (self pairs skipped).
+* Interactions.  Both are the pair interaction of the tabulated scheme:
+  the images |n| <= 1 (spline-softened; beyond the softening for cells)
+  plus the band from a correction table (``oracle.table``).  With theta = 0
+  no cell is ever accepted and the tree force is the direct tabulated force.
+* Radial correction.  The mean radial error (tree minus direct) of the load
+  in ``n_bins`` equal bins of rho on [0, R_dom], accumulated over the given
+  (shift, angle) realisations; applied by linear interpolation between bin
+  centres (constant beyond the first and last centre).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+from oracle import table as ot
+
+KEY_LEVELS = 21
+
+
+def transform(pos, L, shift, angle):
+    c, s = math.cos(angle), math.sin(angle)
+    x = c * pos[0] - s * pos[1]
+    y = s * pos[0] + c * pos[1]
+    z = pos[2] + shift
+    z = z - L * np.floor(z / L)
+    z = np.where(z >= L, 0.0, z)
+    return np.stack([x, y, z])
+
+
+def root_cube(L, R_dom):
+    side = 2.0 * max(L, 2.0 * R_dom)
+    lo = np.array([-0.5 * side, -0.5 * side, 0.5 * L - 0.5 * side])
+    return lo, side
+
+
+def morton_keys(pos_t, lo, side):
+    scale = float(1 << KEY_LEVELS) / side
+    q = np.floor((pos_t - lo[:, None]) * scale)
+    q = np.clip(q, 0, (1 << KEY_LEVELS) - 1).astype(np.int64)
+    key = np.zeros(pos_t.shape[1], dtype=np.int64)
+    for b in range(KEY_LEVELS):
+        key |= ((q[0] >> b) & 1) << (3 * b + 2)
+        key |= ((q[1] >> b) & 1) << (3 * b + 1)
+        key |= ((q[2] >> b) & 1) << (3 * b)
+    return key
+
+
+class Tree:
+    """Cells in depth-first order: level, [start, end) in key order, mass,
+    centre of mass (3), largest softening, leaf flag, skip index."""
+
+    def __init__(self, pos, mass, eps, L, R_dom, shift=0.0, angle=0.0, leaf_size=16):
+        self.L, self.leaf_size = float(L), int(leaf_size)
+        self.lo, self.side = root_cube(L, R_dom)
+        self.pos_t = transform(np.asarray(pos, dtype=np.float64), L, shift, angle)
+        self.keys = morton_keys(self.pos_t, self.lo, self.side)
+        N = self.keys.size
+        self.order = np.lexsort((np.arange(N), self.keys))   # key, then index
+        self.skey = self.keys[self.order]
+        self.sp = self.pos_t[:, self.order]
+        self.sm = np.asarray(mass, dtype=np.float64)[self.order]
+        self.sh = np.asarray(eps, dtype=np.float64)[self.order]
+        self.cells = []
+        self._build(0, 0, N)
+        self.level = np.array([c[0] for c in self.cells])
+        self.start = np.array([c[1] for c in self.cells])
+        self.end = np.array([c[2] for c in self.cells])
+        self.mass = np.array([c[3] for c in self.cells])
+        self.com = np.array([c[4] for c in self.cells]).T
+        self.hmax = np.array([c[5] for c in self.cells])
+        self.leaf = np.array([c[6] for c in self.cells])
+        self.skip = np.array([c[7] for c in self.cells])
+
+    def _build(self, level, start, end):
+        m = self.sm[start:end]
+        M = m.sum()
+        if M > 0:
+            com = (self.sp[:, start:end] * m).sum(axis=1) / M
+        else:  # massless cell: its geometric centre
+            q = self.skey[start]
+            com = self.lo + (self._cell_corner(q, level) + 0.5) * (self.side / (1 << level))
+        leaf = (end - start) <= self.leaf_size or level == KEY_LEVELS
+        idx = len(self.cells)
+        self.cells.append([level, start, end, M, com, self.sh[start:end].max(), leaf, -1])
+        if not leaf:
+            shift = 3 * (KEY_LEVELS - level - 1)
+            digit = (self.skey[start:end] >> shift) & 7
+            s = start
+            for oc in range(8):
+                e = s + int(np.count_nonzero(digit == oc))
+                if e > s:
+                    self._build(level + 1, s, e)
+                s = e
+        self.cells[idx][7] = len(self.cells)
+
+    @staticmethod
+    def _cell_corner(key, level):
+        q = np.zeros(3)
+        for b in range(level):
+            digit = (int(key) >> (3 * (KEY_LEVELS - 1 - b))) & 7
+            q = 2 * q + np.array([(digit >> 2) & 1, (digit >> 1) & 1, digit & 1])
+        return q
+
+    def size(self, k):
+        return self.side / (1 << int(self.level[k]))
+
+
+def box_distance(c, lo, hi, L):
+    """Distance from point c to the box [lo, hi], periodic along z."""
+    dx = max(0.0, lo[0] - c[0], c[0] - hi[0])
+    dy = max(0.0, lo[1] - c[1], c[1] - hi[1])
+    dz = min(max(0.0, lo[2] - cz, cz - hi[2]) for cz in (c[2] - L, c[2], c[2] + L))
+    return math.sqrt(dx * dx + dy * dy + dz * dz)
+
+
+def _interact(tree, tg, src_pos, src_m, src_h, src_id, tab, order, acc):
+    """Targets tg (sorted indices) against sources: near images + band."""
+    L = tree.L
+    tp = tree.sp[:, tg]
+    acc[:, tg] += oracle.pairs(tp, tree.sh[tg], tg, src_pos, src_m, src_h, src_id, L, 1)
+    keep = src_id[None, :] != tg[:, None]                      # (T, S)
+    dx = (tp[0][:, None] - src_pos[0][None, :])[keep]
+    dy = (tp[1][:, None] - src_pos[1][None, :])[keep]
+    t = (tp[2][:, None] - src_pos[2][None, :])[keep]
+    d = t - L * np.floor(t / L + 0.5)
+    m = np.broadcast_to(src_m[None, :], keep.shape)[keep]
+    row = np.broadcast_to(np.arange(tg.size)[:, None], keep.shape)[keep]
+    bx, by, bz = ot.band_pairs(dx, dy, d, L, tab, order)
+    for c, b in enumerate((bx, by, bz)):
+        acc[c, tg] += np.bincount(row, weights=m * b, minlength=tg.size)
+
+
+def tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, shift=0.0, angle=0.0,
+                leaf_size=16, group=64, stats=None):
+    """Accelerations (3, N) of every particle by the octree (G = 1), in the
+    original frame and order."""
+    T = Tree(pos, mass, eps, L, R_dom, shift, angle, leaf_size)
+    N = T.sm.size
+    acc = np.zeros((3, N))     # in key order, transformed frame
+    n_cell = n_part = 0
+    for g0 in range(0, N, group):
+        tg = np.arange(g0, min(g0 + group, N))
+        lo = T.sp[:, tg].min(axis=1)
+        hi = T.sp[:, tg].max(axis=1)
+        hg = T.sh[tg].max()
+        k = 0
+        while k < len(T.cells):
+            d = box_distance(T.com[:, k], lo, hi, L)
+            if T.size(k) < theta * d and d > hg + T.hmax[k]:
+                _interact(T, tg, T.com[:, k:k + 1], T.mass[k:k + 1], T.hmax[k:k + 1],
+                          np.array([-1]), tab, order, acc)
+                n_cell += tg.size
+                k = T.skip[k]
+            elif T.leaf[k]:
+                s = np.arange(T.start[k], T.end[k])
+                _interact(T, tg, T.sp[:, s], T.sm[s], T.sh[s], s, tab, order, acc)
+                n_part += tg.size * s.size
+                k = T.skip[k]
+            else:
+                k += 1
+    if stats is not None:
+        stats.update(cell_interactions=n_cell, particle_interactions=n_part, cells=len(T.cells))
+    out = np.empty_like(acc)
+    out[:, T.order] = acc
+    c, s = math.cos(angle), math.sin(angle)
+    ax = c * out[0] + s * out[1]
+    ay = -s * out[0] + c * out[1]
+    return np.stack([ax, ay, out[2]])
+
+
+# ---------------------------------------------------------------- radial correction
+def radial_bins(pos, acc_err, R_dom, n_bins):
+    """Per-bin sums and counts of the radial component of ``acc_err``."""
+    rho = np.hypot(pos[0], pos[1])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        fr = np.where(rho > 0, (acc_err[0] * pos[0] + acc_err[1] * pos[1]) / rho, 0.0)
+    b = np.clip(np.floor(rho / R_dom * n_bins).astype(np.int64), 0, n_bins - 1)
+    sums = np.bincount(b, weights=fr, minlength=n_bins)
+    counts = np.bincount(b, minlength=n_bins).astype(np.float64)
+    return sums, counts
+
+
+def calibrate(pos, mass, eps, L, R_dom, tab, order, theta, shifts, angles, n_bins,
+              leaf_size=16, group=64):
+    """Mean radial error (tree - direct) per radial bin over the realisations."""
+    direct = ot.forces_table(pos, mass, eps, L, tab, order)
+    sums = np.zeros(n_bins)
+    counts = np.zeros(n_bins)
+    for s, a in zip(shifts, angles):
+        t = tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, s, a, leaf_size, group)
+        ds, dc = radial_bins(pos, t - direct, R_dom, n_bins)
+        sums += ds
+        counts += dc
+    return np.where(counts > 0, sums / np.maximum(counts, 1.0), 0.0)
+
+
+def apply_correction(pos, acc, corr, R_dom):
+    """Subtract the interpolated radial error along rho-hat."""
+    n = len(corr)
+    rho = np.hypot(pos[0], pos[1])
+    centres = (np.arange(n) + 0.5) * (R_dom / n)
+    delta = np.interp(rho, centres, corr)
+    out = acc.copy()
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ux = np.where(rho > 0, pos[0] / rho, 0.0)
+        uy = np.where(rho > 0, pos[1] / rho, 0.0)
+    out[0] -= delta * ux
+    out[1] -= delta * uy
+    return out

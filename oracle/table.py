@@ -112,6 +112,37 @@ def interpolate(tab, delta, r, order):
     return out_z, out_r
 
 
+def band_pairs(dx, dy, d, L, tab, order):
+    """Band acceleration per unit source mass for pair separations (dx, dy)
+    and minimum-image axial offsets d (arrays): the interpolated table where
+    rho/L <= r_max, the exact band beyond (the complete band for a complete
+    table).  Returns (ax, ay, az) per unit G m."""
+    dx = np.asarray(dx, dtype=np.float64)
+    dy = np.asarray(dy, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    rho = np.hypot(dx, dy)
+    r = rho / L
+    inside = r <= tab.r_max
+    Fz = np.zeros_like(d)
+    Fr = np.zeros_like(d)
+    if inside.any():
+        tz, tr = interpolate(tab, np.abs(d[inside]) / L, r[inside], order)
+        Fz[inside] = np.sign(d[inside]) * tz
+        Fr[inside] = tr
+    out = ~inside
+    if out.any():
+        if tab.complete:
+            from oracle import ewald as ew
+            Fz[out], Fr[out] = ew.band_direct(d[out] / L, r[out])
+        else:
+            Fz[out], Fr[out], _ = oracle.image_band(d[out] / L, r[out], 1.0, 2, tab.n_far)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ux = np.where(rho > 0, dx / rho, 0.0)
+        uy = np.where(rho > 0, dy / rho, 0.0)
+    s = 1.0 / (L * L)
+    return s * Fr * ux, s * Fr * uy, s * Fz
+
+
 def forces_table(pos, mass, eps, L, tab, order, targets=None):
     """FP64 accelerations of the tabulated scheme: exact images |n| <= 1
     (spline-softened) plus the interpolated band for pairs with
@@ -125,31 +156,10 @@ def forces_table(pos, mass, eps, L, tab, order, targets=None):
     acc = near.copy()
     for k, i in enumerate(tg):
         j = np.arange(N) != i
-        dx = pos[0, i] - pos[0, j]
-        dy = pos[1, i] - pos[1, j]
         t = z[i] - z[j]
         d = t - L * np.floor(t / L + 0.5)
-        rho = np.hypot(dx, dy)
-        r = rho / L
-        inside = r <= tab.r_max
-        Fz = np.zeros_like(d)
-        Fr = np.zeros_like(d)
-        if inside.any():
-            tz, tr = interpolate(tab, np.abs(d[inside]) / L, r[inside], order)
-            Fz[inside] = np.sign(d[inside]) * tz
-            Fr[inside] = tr
-        out = ~inside
-        if out.any():
-            if tab.complete:
-                from oracle import ewald as ew
-                Fz[out], Fr[out] = ew.band_direct(d[out] / L, r[out])
-            else:
-                Fz[out], Fr[out], _ = oracle.image_band(d[out] / L, r[out], 1.0, 2, tab.n_far)
-        m = mass[j] / (L * L)
-        with np.errstate(invalid="ignore", divide="ignore"):
-            ux = np.where(rho > 0, dx / rho, 0.0)
-            uy = np.where(rho > 0, dy / rho, 0.0)
-        acc[0, k] += np.sum(m * Fr * ux)
-        acc[1, k] += np.sum(m * Fr * uy)
-        acc[2, k] += np.sum(m * Fz)
+        bx, by, bz = band_pairs(pos[0, i] - pos[0, j], pos[1, i] - pos[1, j], d, L, tab, order)
+        acc[0, k] += np.sum(mass[j] * bx)
+        acc[1, k] += np.sum(mass[j] * by)
+        acc[2, k] += np.sum(mass[j] * bz)
     return acc

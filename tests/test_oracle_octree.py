@@ -1,0 +1,135 @@
+"""Pins of the octree oracle: with theta = 0 it is the direct tabulated force
+(any shift and rotation of the domain); the cells partition the particles,
+carry the mass and centre of mass of their content, respect the leaf size
+and the depth-first skip structure; Morton keys interleave the cell
+coordinates; the error grows with the opening angle and is bounded for small
+angles; a group walk is at least as accurate as the per-particle walk; the
+radial calibration removes the mean radial bias it measures (Sect. 2.4,
+"Octree")."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import octree as oc
+from oracle import table as ot
+
+R = synth.r_max()
+
+
+@pytest.fixture(scope="module")
+def load():
+    return synth.cylinder_load(700, seed=17)
+
+
+@pytest.fixture(scope="module")
+def tab():
+    return ot.Table(24, 16, 6.5)
+
+
+@pytest.fixture(scope="module")
+def direct(load, tab):
+    return ot.forces_table(load.pos, load.mass, load.eps, load.L, tab, 1)
+
+
+def rel(a, ref):
+    return np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
+
+
+@pytest.mark.parametrize("shift,angle", [(0.0, 0.0), (0.37, 2.1), (0.99, -0.4)])
+def test_zero_opening_angle_is_the_direct_force(load, tab, direct, shift, angle):
+    a = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.0, shift, angle,
+                       leaf_size=8, group=32)
+    assert rel(a, direct).max() < 1e-12
+
+
+def test_morton_key_interleaves_cell_coordinates():
+    lo, side = oc.root_cube(1.0, R)
+    rng = np.random.default_rng(3)
+    q = rng.integers(0, 1 << 21, size=(3, 50))
+    pos = lo[:, None] + (q + 0.5) * (side / (1 << 21))
+    key = oc.morton_keys(pos, lo, side)
+    for k in range(50):
+        back = [0, 0, 0]
+        for b in range(21):
+            back[0] |= ((int(key[k]) >> (3 * b + 2)) & 1) << b
+            back[1] |= ((int(key[k]) >> (3 * b + 1)) & 1) << b
+            back[2] |= ((int(key[k]) >> (3 * b)) & 1) << b
+        assert back == [int(q[0, k]), int(q[1, k]), int(q[2, k])]
+
+
+def test_cells_form_a_valid_tree(load):
+    T = oc.Tree(load.pos, load.mass, load.eps, load.L, R, 0.2, 0.7, leaf_size=6)
+    n = len(T.cells)
+    # leaves partition the particles in key order
+    leaves = [(T.start[k], T.end[k]) for k in range(n) if T.leaf[k]]
+    assert leaves[0][0] == 0 and leaves[-1][1] == load.N
+    assert all(a[1] == b[0] for a, b in zip(leaves[:-1], leaves[1:]))
+    for k in range(n):
+        cnt = T.end[k] - T.start[k]
+        assert cnt >= 1
+        if T.leaf[k]:
+            assert cnt <= 6 or T.level[k] == oc.KEY_LEVELS
+            assert T.skip[k] == k + 1
+        else:
+            # children follow directly, cover the parent's range, one level down
+            kids = []
+            c = k + 1
+            while c < T.skip[k]:
+                kids.append(c)
+                c = T.skip[c]
+            assert c == T.skip[k]
+            assert all(T.level[c] == T.level[k] + 1 for c in kids)
+            assert T.start[kids[0]] == T.start[k] and T.end[kids[-1]] == T.end[k]
+            assert T.mass[k] == pytest.approx(sum(T.mass[c] for c in kids), rel=1e-13)
+        s = slice(T.start[k], T.end[k])
+        assert T.mass[k] == pytest.approx(T.sm[s].sum(), rel=1e-13)
+        np.testing.assert_allclose(T.com[:, k], (T.sp[:, s] * T.sm[s]).sum(axis=1) / T.sm[s].sum(),
+                                   rtol=1e-12, atol=1e-14)
+        # the centre of mass lies in the cell's cube
+        corner = T.lo + oc.Tree._cell_corner(T.skey[T.start[k]], int(T.level[k])) * T.size(k)
+        assert np.all(T.com[:, k] >= corner - 1e-12) and np.all(T.com[:, k] <= corner + T.size(k) + 1e-12)
+        assert T.hmax[k] == T.sh[s].max()
+    # particles sit in key order
+    assert np.all(np.diff(T.skey) >= 0)
+
+
+def test_error_grows_with_opening_angle(load, tab, direct):
+    means = []
+    for theta in (0.25, 0.5, 0.8):
+        a = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, theta, 0.1, 0.3,
+                           leaf_size=8, group=16)
+        means.append(rel(a, direct).mean())
+    assert means[0] < means[1] < means[2]
+    assert means[0] < 2e-3
+
+
+def test_group_walk_is_at_least_as_accurate(load, tab, direct):
+    g = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.7, 0.5, 1.0,
+                       leaf_size=8, group=32)
+    s = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.7, 0.5, 1.0,
+                       leaf_size=8, group=1)
+    assert rel(g, direct).mean() <= rel(s, direct).mean()
+
+
+def test_radial_calibration_removes_the_mean_radial_bias(load, tab, direct):
+    theta, nb = 0.9, 8
+    rng = np.random.default_rng(5)
+    shifts = rng.random(3) * load.L
+    angles = rng.random(3) * 2 * math.pi
+    corr = oc.calibrate(load.pos, load.mass, load.eps, load.L, R, tab, 1, theta, shifts, angles, nb,
+                        leaf_size=8, group=16)
+    assert np.abs(corr).max() > 0
+    # on a realisation used for the calibration the corrected bias is smaller
+    a = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, theta, shifts[0], angles[0],
+                       leaf_size=8, group=16)
+    ac = oc.apply_correction(load.pos, a, corr, R)
+    s0, c0 = oc.radial_bins(load.pos, a - direct, R, nb)
+    s1, c1 = oc.radial_bins(load.pos, ac - direct, R, nb)
+    ok = c0 > 0
+    assert np.abs(s1[ok] / c1[ok]).mean() < np.abs(s0[ok] / c0[ok]).mean()
+    # theta = 0 has nothing to correct
+    z = oc.calibrate(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.0, shifts[:1], angles[:1], nb,
+                     leaf_size=8, group=16)
+    assert np.abs(z).max() < 1e-12
