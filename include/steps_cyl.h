@@ -301,6 +301,80 @@ int steps_cyl_forces_table(const double *pos, const double *mass, const double *
                            float *out_acc, float *out_pot, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Barnes-Hut octree (Sect. 2.4, "Octree": cubic cells, root cell twice the
+ * largest linear size of the volume, random shifts along the axis and
+ * rotations about it at every step, radial correction table measured on the
+ * initial load).
+ *
+ * The root cube has side S0 = 2 max(L, 2 R_dom) and centre (0, 0, L/2) in
+ * the frame rotated by `angle` about the axis and shifted by `shift` along
+ * it (z wrapped into [0, L)); R_dom must bound the particles' radius.  Cells
+ * are split while they hold more than leaf_size particles (down to level
+ * 21); each acts through its mass at its centre of mass.  Particles are
+ * taken in Morton order in groups of 64 that walk the tree together: a cell
+ * is accepted for a group when S0/2^level < theta d and
+ * d > h_group + h_cell, with d the distance (periodic in z) from the cell's
+ * centre of mass to the group's bounding box and h the largest softening
+ * lengths; otherwise it is opened, and an opened leaf contributes its
+ * particles.  Cells and particles interact through the pair of the tabulated
+ * scheme (exact images |n| <= 1, softened, plus the table's band), so
+ * theta = 0 gives steps_cyl_forces_table's forces.
+ *
+ * The tree object owns its device buffers (sized on first use and grown
+ * when N grows; the build and the walk allocate nothing else) and the radial
+ * correction.  Calls on one tree must not overlap.
+ * ---------------------------------------------------------------------- */
+typedef struct steps_cyl_tree steps_cyl_tree;   /* opaque */
+
+/* 1 <= leaf_size <= 64.  No device work. */
+int steps_cyl_tree_create(int leaf_size, steps_cyl_tree **out);
+
+/* Releases the tree and its buffers (NULL is ignored). */
+void steps_cyl_tree_destroy(steps_cyl_tree *tree);
+
+/* Builds the tree for pos (device [3][N] FP64), mass, eps (device [N]) in
+ * the frame given by shift and angle, walks it and writes out_acc (device
+ * [3][N] FP32, caller's order and frame, G = 1).  table and order (1 CIC,
+ * 2 TSC) as steps_cyl_forces_table; theta >= 0 the opening angle.  correct:
+ * subtract the radial correction set by steps_cyl_tree_set_correction or
+ * steps_cyl_tree_calibrate (STEPS_EINVAL if none is set).  1 <= N <= 2^30.
+ * Synchronises the stream once per tree level during the build. */
+int steps_cyl_tree_forces(steps_cyl_tree *tree, const double *pos, const double *mass,
+                          const double *eps, int64_t N, double L, double R_dom,
+                          const steps_cyl_table *table, int order, double theta,
+                          double shift, double angle, int correct, float *out_acc,
+                          hipStream_t stream);
+
+/* Radial correction: mean radial error (tree minus direct tabulated force)
+ * per bin of rho, bins of width R_dom/n_bins, over n_real realisations
+ * (host arrays shifts[n_real], angles[n_real], the caller's random draws);
+ * stored in the tree and copied to out_corr (host [n_bins], may be NULL).
+ * Applied by linear interpolation between bin centres, constant beyond the
+ * first and the last.  1 <= n_real <= 1024, 1 <= n_bins <= 256.  Synchronous. */
+int steps_cyl_tree_calibrate(steps_cyl_tree *tree, const double *pos, const double *mass,
+                             const double *eps, int64_t N, double L, double R_dom,
+                             const steps_cyl_table *table, int order, double theta,
+                             const double *shifts, const double *angles, int n_real,
+                             int n_bins, double *out_corr, hipStream_t stream);
+
+/* Sets (host corr[n_bins], bins of width R_dom/n_bins) or, with n_bins = 0,
+ * clears the radial correction.  Synchronous. */
+int steps_cyl_tree_set_correction(steps_cyl_tree *tree, const double *corr, int n_bins,
+                                  double R_dom);
+
+/* Statistics of the last walk: cells, and cell and particle interactions
+ * summed over targets.  Any output may be NULL.  Synchronous. */
+int steps_cyl_tree_info(const steps_cyl_tree *tree, int64_t *n_cells,
+                        int64_t *cell_interactions, int64_t *particle_interactions);
+
+/* The cells of the last build in depth-first order (host arrays of n_cells
+ * entries; com is [3][n_cells]) and the caller's index of each particle in
+ * key order (host_order[N]).  Any output may be NULL.  Synchronous. */
+int steps_cyl_tree_cells(const steps_cyl_tree *tree, int *host_level, int *host_start,
+                         int *host_count, int *host_skip, int *host_leaf, double *host_mass,
+                         double *host_com, int *host_order);
+
+/* ------------------------------------------------------------------------
  * Time integration (Sect. 2.1, eq. ComovingEquationsOfMotionCylindrical and
  * its kick-drift-kick integrator in cosmic time; Sect. 2.3 background).
  *

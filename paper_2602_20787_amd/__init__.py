@@ -24,6 +24,9 @@ __all__ = [
     "CorrectionTable", "steps_cyl_table_create", "steps_cyl_table_destroy",
     "steps_cyl_table_values", "steps_cyl_forces_table", "steps_cyl_table_create_ewald",
     "steps_cyl_table_values_f64", "steps_cyl_table_info", "STEPS_EWALD_BESSEL", "STEPS_EWALD_PRINTED",
+    "Octree", "steps_cyl_tree_create", "steps_cyl_tree_destroy", "steps_cyl_tree_forces",
+    "steps_cyl_tree_calibrate", "steps_cyl_tree_set_correction", "steps_cyl_tree_info",
+    "steps_cyl_tree_cells",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -107,6 +110,14 @@ _SIGNATURES = {
     "steps_cyl_table_create_ewald": [_I32, _I32, _F64, _F64, _I32, _I32, _I32, _VP, _PP],
     "steps_cyl_table_values_f64": [_VP, _VP],
     "steps_cyl_table_info": [_VP, _VP, _VP, _VP, _VP],
+    "steps_cyl_tree_create": [_I32, _PP],
+    "steps_cyl_tree_forces": [_VP, _VP, _VP, _VP, _I64, _F64, _F64, _VP, _I32, _F64, _F64, _F64, _I32,
+                              _VP, _VP],
+    "steps_cyl_tree_calibrate": [_VP, _VP, _VP, _VP, _I64, _F64, _F64, _VP, _I32, _F64, _VP, _VP,
+                                 _I32, _I32, _VP, _VP],
+    "steps_cyl_tree_set_correction": [_VP, _VP, _I32, _F64],
+    "steps_cyl_tree_info": [_VP, _VP, _VP, _VP],
+    "steps_cyl_tree_cells": [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
     "steps_cyl_forces_table": [_VP, _VP, _VP, _I64, _F64, _VP, _I32, _VP, _I64, _VP, _VP, _VP],
 }
 
@@ -127,6 +138,8 @@ def lib():
         L.steps_cyl_mlp_destroy.restype = None
         L.steps_cyl_table_destroy.argtypes = [_VP]
         L.steps_cyl_table_destroy.restype = None
+        L.steps_cyl_tree_destroy.argtypes = [_VP]
+        L.steps_cyl_tree_destroy.restype = None
         L.steps_cyl_last_error.restype = ctypes.c_char_p
         L.steps_cyl_last_error.argtypes = []
         L.steps_cyl_version.restype = ctypes.c_char_p
@@ -588,3 +601,102 @@ def steps_cyl_forces_table(pos, mass, eps, L, table, order=2, targets=None, out_
     _check(lib().steps_cyl_forces_table(p_pos, p_m, p_e, N, float(L), h, int(order), p_t, T,
                                         p_acc, p_pot, _stream(stream, pos.device)))
     return out_acc, (out_pot if potential else None)
+
+
+# ---------------------------------------------------------------- octree
+def steps_cyl_tree_create(leaf_size=16):
+    h = ctypes.c_void_p()
+    _check(lib().steps_cyl_tree_create(int(leaf_size), ctypes.byref(h)))
+    return h.value
+
+
+def steps_cyl_tree_destroy(handle):
+    if handle:
+        lib().steps_cyl_tree_destroy(handle)
+
+
+def _table_handle(table):
+    return table.handle if isinstance(table, CorrectionTable) else table
+
+
+def steps_cyl_tree_forces(tree, pos, mass, eps, L, R_dom, table, order=1, theta=0.5, shift=0.0,
+                          angle=0.0, correct=False, out_acc=None, stream=None):
+    import torch
+    N, p_pos, p_m, p_e = _sources(pos, mass, eps)
+    if out_acc is None:
+        out_acc = torch.empty((3, N), dtype=torch.float32, device=pos.device)
+    p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * N)
+    h = tree.handle if isinstance(tree, Octree) else tree
+    _check(lib().steps_cyl_tree_forces(h, p_pos, p_m, p_e, N, float(L), float(R_dom), _table_handle(table),
+                                       int(order), float(theta), float(shift), float(angle),
+                                       1 if correct else 0, p_acc, _stream(stream, pos.device)))
+    return out_acc
+
+
+def steps_cyl_tree_calibrate(tree, pos, mass, eps, L, R_dom, table, order, theta, shifts, angles,
+                             n_bins, stream=None):
+    """Measures and stores the radial correction; returns it (host FP64)."""
+    import numpy as np
+    N, p_pos, p_m, p_e = _sources(pos, mass, eps)
+    sh = np.ascontiguousarray(shifts, dtype=np.float64)
+    an = np.ascontiguousarray(angles, dtype=np.float64)
+    if sh.shape != an.shape:
+        raise ValueError("shifts and angles differ in length")
+    out = np.zeros(int(n_bins), dtype=np.float64)
+    h = tree.handle if isinstance(tree, Octree) else tree
+    _check(lib().steps_cyl_tree_calibrate(h, p_pos, p_m, p_e, N, float(L), float(R_dom),
+                                          _table_handle(table), int(order), float(theta),
+                                          sh.ctypes.data, an.ctypes.data, sh.size, int(n_bins),
+                                          out.ctypes.data, _stream(stream, pos.device)))
+    return out
+
+
+def steps_cyl_tree_set_correction(tree, corr, R_dom):
+    import numpy as np
+    c = np.ascontiguousarray(corr if corr is not None else [], dtype=np.float64)
+    h = tree.handle if isinstance(tree, Octree) else tree
+    _check(lib().steps_cyl_tree_set_correction(h, c.ctypes.data if c.size else None, c.size,
+                                               float(R_dom)))
+
+
+def steps_cyl_tree_info(tree):
+    """(cells, cell interactions, particle interactions) of the last walk."""
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    h = tree.handle if isinstance(tree, Octree) else tree
+    _check(lib().steps_cyl_tree_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def steps_cyl_tree_cells(tree, N):
+    """Cells of the last build (depth-first) and the particles' key order."""
+    import numpy as np
+    n = steps_cyl_tree_info(tree)[0]
+    out = {k: np.empty(n, dtype=np.int32) for k in ("level", "start", "count", "skip", "leaf")}
+    out["mass"] = np.empty(n, dtype=np.float64)
+    out["com"] = np.empty((3, n), dtype=np.float64)
+    out["order"] = np.empty(int(N), dtype=np.int32)
+    h = tree.handle if isinstance(tree, Octree) else tree
+    _check(lib().steps_cyl_tree_cells(h, out["level"].ctypes.data, out["start"].ctypes.data,
+                                      out["count"].ctypes.data, out["skip"].ctypes.data,
+                                      out["leaf"].ctypes.data, out["mass"].ctypes.data,
+                                      out["com"].ctypes.data, out["order"].ctypes.data))
+    return out
+
+
+class Octree:
+    """Owning wrapper of a tree handle."""
+
+    def __init__(self, leaf_size=16):
+        self.leaf_size = leaf_size
+        self.handle = steps_cyl_tree_create(leaf_size)
+
+    def close(self):
+        if self.handle:
+            steps_cyl_tree_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

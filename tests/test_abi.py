@@ -218,3 +218,34 @@ def test_table_calls_reject_null_handles():
     assert L.steps_cyl_table_info(None, None, None, None, None) == sc.STEPS_EINVAL
     assert L.steps_cyl_forces_table(P, P, P, 10, 1.0, None, 1, None, 10, P, None, None) == sc.STEPS_EINVAL
     L.steps_cyl_table_destroy(None)
+
+
+def test_tree_calls_reject_bad_arguments():
+    L = sc.lib()
+    P = ctypes.c_void_p(64)
+    h = ctypes.c_void_p()
+    assert L.steps_cyl_tree_create(0, ctypes.byref(h)) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_create(65, ctypes.byref(h)) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_create(16, None) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_create(16, ctypes.byref(h)) == sc.STEPS_OK   # host object only
+    t = h.value
+    f = L.steps_cyl_tree_forces
+    assert f(None, P, P, P, 10, 1.0, 3.0, P, 1, 0.5, 0.0, 0.0, 0, P, None) == sc.STEPS_EINVAL
+    assert f(t, P, P, P, 10, 1.0, 3.0, None, 1, 0.5, 0.0, 0.0, 0, P, None) == sc.STEPS_EINVAL
+    assert f(t, P, P, P, 0, 1.0, 3.0, P, 1, 0.5, 0.0, 0.0, 0, P, None) == sc.STEPS_EINVAL
+    assert f(t, P, P, P, 10, 1.0, -3.0, P, 1, 0.5, 0.0, 0.0, 0, P, None) == sc.STEPS_EINVAL
+    assert f(t, P, P, P, 10, 1.0, 3.0, P, 3, 0.5, 0.0, 0.0, 0, P, None) == sc.STEPS_EINVAL
+    assert f(t, P, P, P, 10, 1.0, 3.0, P, 1, -0.5, 0.0, 0.0, 0, P, None) == sc.STEPS_EINVAL
+    assert f(t, P, P, P, 10, 1.0, 3.0, P, 1, 0.5, float("nan"), 0.0, 0, P, None) == sc.STEPS_EINVAL
+    assert f(t, P, P, P, 10, 1.0, 3.0, P, 1, 0.5, 0.0, 0.0, 1, P, None) == sc.STEPS_EINVAL
+    assert "no radial correction" in sc.steps_cyl_last_error()
+    c = L.steps_cyl_tree_calibrate
+    assert c(t, P, P, P, 10, 1.0, 3.0, P, 1, 0.5, None, P, 2, 8, None, None) == sc.STEPS_EINVAL
+    assert c(t, P, P, P, 10, 1.0, 3.0, P, 1, 0.5, P, P, 0, 8, None, None) == sc.STEPS_EINVAL
+    assert c(t, P, P, P, 10, 1.0, 3.0, P, 1, 0.5, P, P, 2, 300, None, None) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_set_correction(t, None, 4, 3.0) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_set_correction(t, None, 0, 3.0) == sc.STEPS_OK
+    assert L.steps_cyl_tree_info(None, None, None, None) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_cells(None, None, None, None, None, None, None, None, None) == sc.STEPS_EINVAL
+    L.steps_cyl_tree_destroy(t)
+    L.steps_cyl_tree_destroy(None)

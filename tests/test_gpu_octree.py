@@ -1,0 +1,172 @@
+"""GPU parity of the Barnes-Hut octree (Sect. 2.4) against its FP64 oracle.
+
+Bars: the tree's integer structure (depth-first cells: level, particle
+range, skip link, leaf flag; the particles' key order) and the interaction
+counts are bit-exact (both sides take the cell and acceptance decisions in
+FP64 with the same operations); cell masses and centres of mass to FP64
+summation-order round-off; forces to 2e-5 relative (FP32 pair arithmetic
+and FP32 table nodes, as for the tabulated scheme); theta = 0 reproduces
+the direct tabulated kernel to FP32 summation-order round-off; the radial
+correction to 1e-5 of the mean force (it is a mean of differences of FP32
+forces).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import octree as oc
+from oracle import table as ot
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+R = synth.r_max()
+
+
+@pytest.fixture(scope="module")
+def sc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_20787_amd as m
+    return m
+
+
+def to_dev(p):
+    d = torch.device("cuda:0")
+    return (torch.from_numpy(p.pos).to(d), torch.from_numpy(p.mass).to(d),
+            torch.from_numpy(p.eps).to(d))
+
+
+def rel(a, ref):
+    return np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
+
+
+@pytest.mark.parametrize("N,leaf,shift,angle", [(3000, 16, 0.3, 1.2), (777, 1, 0.0, 0.0), (40, 64, 0.9, -2.0)])
+def test_tree_structure_matches_oracle(sc, N, leaf, shift, angle):
+    p = synth.cylinder_load(N, seed=31)
+    t = sc.Octree(leaf)
+    tab = sc.CorrectionTable(16, 12, 6.5, 1024)
+    sc.steps_cyl_tree_forces(t, *to_dev(p), p.L, R, tab, 1, 0.5, shift, angle)
+    torch.cuda.synchronize()
+    g = sc.steps_cyl_tree_cells(t, N)
+    T = oc.Tree(p.pos, p.mass, p.eps, p.L, R, shift, angle, leaf)
+    print(f"N={N} leaf={leaf}: {len(T.cells)} cells, depth {T.level.max()}")
+    np.testing.assert_array_equal(g["order"], T.order)
+    np.testing.assert_array_equal(g["level"], T.level)
+    np.testing.assert_array_equal(g["start"], T.start)
+    np.testing.assert_array_equal(g["count"], T.end - T.start)
+    np.testing.assert_array_equal(g["skip"], T.skip)
+    np.testing.assert_array_equal(g["leaf"].astype(bool), T.leaf)
+    np.testing.assert_allclose(g["mass"], T.mass, rtol=1e-13)
+    np.testing.assert_allclose(g["com"], T.com, rtol=1e-12, atol=1e-13)
+    t.close()
+    tab.close()
+
+
+def test_zero_opening_angle_is_the_direct_kernel(sc):
+    p = synth.cylinder_load(4000, seed=32)
+    t = sc.Octree(16)
+    tab = sc.CorrectionTable(32, 40, 6.5, 1024)
+    pos, m, e = to_dev(p)
+    a = sc.steps_cyl_tree_forces(t, pos, m, e, p.L, R, tab, 1, 0.0, 0.4, 0.8)
+    d, _ = sc.steps_cyl_forces_table(pos, m, e, p.L, tab, order=1, potential=False)
+    torch.cuda.synchronize()
+    err = rel(a.double().cpu().numpy(), d.double().cpu().numpy())
+    assert err.max() <= 2e-6, err.max()
+    n_cells, n_c, n_p = sc.steps_cyl_tree_info(t)
+    assert n_c == 0 and n_p == p.N * p.N
+    t.close()
+    tab.close()
+
+
+@pytest.mark.parametrize("theta,order", [(0.3, 1), (0.6, 1), (1.0, 1), (0.6, 2)])
+def test_tree_forces_match_oracle(sc, theta, order):
+    p = synth.clustered_load(2000, n_clumps=4, clump_frac=0.05, seed=33)
+    t = sc.Octree(16)
+    tab = sc.CorrectionTable(24, 16, 6.5, 1024)
+    a = sc.steps_cyl_tree_forces(t, *to_dev(p), p.L, R, tab, order, theta, 0.6, 2.5)
+    torch.cuda.synchronize()
+    st = {}
+    ref = oc.tree_forces(p.pos, p.mass, p.eps, p.L, R, ot.Table(24, 16, 6.5), order, theta, 0.6, 2.5,
+                         leaf_size=16, group=64, stats=st)
+    n_cells, n_c, n_p = sc.steps_cyl_tree_info(t)
+    err = rel(a.double().cpu().numpy(), ref)
+    print(f"theta={theta} order={order}: cells {n_cells}, cell/particle interactions {n_c}/{n_p}, "
+          f"max rel err {err.max():.2e}")
+    assert (n_cells, n_c, n_p) == (st["cells"], st["cell_interactions"], st["particle_interactions"])
+    assert err.max() <= 2e-5
+    t.close()
+    tab.close()
+
+
+def test_radial_calibration_matches_oracle(sc):
+    p = synth.cylinder_load(1500, seed=34)
+    t = sc.Octree(8)
+    tab = sc.CorrectionTable(24, 16, 6.5, 1024)
+    otab = ot.Table(24, 16, 6.5)
+    theta, nb = 0.9, 8
+    rng = np.random.default_rng(35)
+    shifts = rng.random(3) * p.L
+    angles = rng.random(3) * 2 * math.pi
+    pos, m, e = to_dev(p)
+    corr = sc.steps_cyl_tree_calibrate(t, pos, m, e, p.L, R, tab, 1, theta, shifts, angles, nb)
+    ref = oc.calibrate(p.pos, p.mass, p.eps, p.L, R, otab, 1, theta, shifts, angles, nb,
+                       leaf_size=8, group=64)
+    direct = ot.forces_table(p.pos, p.mass, p.eps, p.L, otab, 1)
+    scale = np.linalg.norm(direct, axis=0).mean()
+    print("correction", corr, "oracle", ref)
+    np.testing.assert_allclose(corr, ref, rtol=0, atol=1e-5 * scale)
+    # the corrected walk subtracts it
+    a = sc.steps_cyl_tree_forces(t, pos, m, e, p.L, R, tab, 1, theta, 0.2, 0.5, correct=True)
+    torch.cuda.synchronize()
+    b = oc.apply_correction(p.pos, oc.tree_forces(p.pos, p.mass, p.eps, p.L, R, otab, 1, theta, 0.2, 0.5,
+                                                  leaf_size=8, group=64), ref, R)
+    assert rel(a.double().cpu().numpy(), b).max() <= 2e-5
+    sc.steps_cyl_tree_set_correction(t, None, R)
+    with pytest.raises(sc.StepsError):
+        sc.steps_cyl_tree_forces(t, pos, m, e, p.L, R, tab, 1, theta, correct=True)
+    t.close()
+    tab.close()
+
+
+def test_force_error_statistics_follow_the_opening_angle(sc):
+    # Fig. 3's measures on a 2^15-particle load: mean relative error, mean
+    # radial and tangential ratio against the direct forces, with and
+    # without the radial correction
+    p = synth.cylinder_load(1 << 15, seed=36)
+    pos, m, e = to_dev(p)
+    tab = sc.CorrectionTable(128, 144, 6.4, 1024)
+    d, _ = sc.steps_cyl_forces_table(pos, m, e, p.L, tab, order=1, potential=False)
+    d = d.double().cpu().numpy()
+    x, y = p.pos[0], p.pos[1]
+    rho = np.hypot(x, y)
+    ur = np.stack([x / rho, y / rho])
+    ut = np.stack([-y / rho, x / rho])
+    rng = np.random.default_rng(37)
+    rows = []
+    for theta in (0.3, 0.5, 0.7, 0.9):
+        t = sc.Octree(16)
+        sc.steps_cyl_tree_calibrate(t, pos, m, e, p.L, R, tab, 1, theta, rng.random(4) * p.L,
+                                    rng.random(4) * 2 * math.pi, 32)
+        s, a = rng.random() * p.L, rng.random() * 2 * math.pi
+        raw = sc.steps_cyl_tree_forces(t, pos, m, e, p.L, R, tab, 1, theta, s, a).double().cpu().numpy()
+        cor = sc.steps_cyl_tree_forces(t, pos, m, e, p.L, R, tab, 1, theta, s, a,
+                                       correct=True).double().cpu().numpy()
+        _, n_c, n_p = sc.steps_cyl_tree_info(t)
+        t.close()
+        out = [theta, (n_c + n_p) / p.N]
+        for f in (raw, cor):
+            out += [rel(f, d).mean(), np.mean((f[:2] * ur).sum(0) / (d[:2] * ur).sum(0)),
+                    np.median((f[:2] * ut).sum(0) / (d[:2] * ut).sum(0))]
+        rows.append(out)
+        print("theta {:.1f}: {:.0f} interactions/particle; raw mean err {:.2e} radial ratio {:.5f} "
+              "tangential {:.4f}; corrected {:.2e} {:.5f} {:.4f}".format(*out))
+    err = [r[2] for r in rows]
+    assert all(a < b for a, b in zip(err[:-1], err[1:]))
+    assert err[1] < 1e-2
+    # the correction brings the mean radial ratio closer to one
+    for r in rows[1:]:
+        assert abs(r[6] - 1) <= abs(r[3] - 1) + 1e-4
+    tab.close()
