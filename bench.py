@@ -271,6 +271,60 @@ def learned_leg(args, dev):
     }
 
 
+def tree_leg(args, dev):
+    """Barnes-Hut octree (complete 144 x 128 table, CIC) on the N = args.tree_n
+    cylinder load: build + walk time per evaluation at several opening
+    angles (random shift and rotation each time), interactions per particle,
+    and the error against the direct tabulated force with the same table on
+    4096 sampled targets."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2602_20787_amd as sc
+
+    N = args.tree_n
+    p = synth.cylinder_load(N, seed=0)
+    pos = torch.from_numpy(p.pos).to(dev)
+    m = torch.from_numpy(p.mass).to(dev)
+    e = torch.from_numpy(p.eps).to(dev)
+    R = synth.r_max()
+    stream = torch.cuda.current_stream(dev)
+    table = sc.CorrectionTable.ewald(128, 144, 6.4, 2.0, 5, 12)
+    t = torch.from_numpy(synth.target_sample(N, 4096, seed=11)).to(dev)
+    ref, _ = sc.steps_cyl_forces_table(pos, m, e, p.L, table, order=1, targets=t, potential=False)
+    ref = ref.double()
+    tree = sc.Octree(16)
+    rng = np.random.default_rng(12)
+    acc = torch.empty((3, N), dtype=torch.float32, device=dev)
+    sc.steps_cyl_tree_forces(tree, pos, m, e, p.L, R, table, 1, 0.5, 0.0, 0.0, out_acc=acc)  # warm-up
+    torch.cuda.synchronize()
+    rows = []
+    for theta in args.tree_theta:
+        ms = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            sc.steps_cyl_tree_forces(tree, pos, m, e, p.L, R, table, 1, theta, rng.random() * p.L,
+                                     rng.random() * 2 * math.pi, out_acc=acc, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        _, n_c, n_p = sc.steps_cyl_tree_info(tree)
+        a = acc[:, t].double()
+        err = (torch.linalg.norm(a - ref, dim=0) / torch.linalg.norm(ref, dim=0)).cpu().numpy()
+        rows.append({"theta": theta, "ms": round(float(np.median(ms)), 2),
+                     "interactions_per_particle": round((n_c + n_p) / N, 1),
+                     "mean_rel_err": float(f"{err.mean():.3e}"), "max_rel_err": float(f"{err.max():.3e}")})
+        print(f"[bench] tree N={N} theta={theta} {rows[-1]}", file=sys.stderr, flush=True)
+    tree.close()
+    table.close()
+    return {"N": N, "workload": f"stereographic cylinder load N={N} (seed 0), octree with leaf size 16 "
+                                "and 64-particle groups, complete 144x128 table (CIC); error vs the "
+                                "direct tabulated force on 4096 targets", "runs": rows}
+
+
 def copy_leg(dev):
     """A 256 MiB device-to-device copy, the yardstick for HBM byte counters."""
     import torch
@@ -303,6 +357,9 @@ def main():
                     help="particles of the learned-correction comparison (0 skips it)")
     ap.add_argument("--exact-steps", type=int, default=None,
                     help="timed exact evaluations (default --steps); 0 skips the exact leg")
+    ap.add_argument("--tree-n", type=int, default=1 << 20,
+                    help="particles of the octree leg (0 skips it)")
+    ap.add_argument("--tree-theta", type=float, nargs="+", default=[0.3, 0.5, 0.7])
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -321,6 +378,8 @@ def main():
         "metric": METRIC, "value": None, "unit": "G pair-interactions/s", "n_gpus": 1}
     if args.learned_n:
         out["learned"] = learned_leg(args, dev)
+    if args.tree_n:
+        out["octree"] = tree_leg(args, dev)
     if args.copy_calib:
         out["copy_calib"] = copy_leg(dev)
     print(json.dumps(out), flush=True)

@@ -6,7 +6,8 @@ counts are bit-exact (both sides take the cell and acceptance decisions in
 FP64 with the same operations); cell masses and centres of mass to FP64
 summation-order round-off; forces to 2e-5 relative (FP32 pair arithmetic
 and FP32 table nodes, as for the tabulated scheme); theta = 0 reproduces
-the direct tabulated kernel to FP32 summation-order round-off; the radial
+the direct tabulated kernel to FP32 summation-order round-off (2e-5: each
+side is within 1e-5 of FP64 and sums the same pairs in another order); the radial
 correction to 1e-5 of the mean force (it is a mean of differences of FP32
 forces).
 """
@@ -74,7 +75,9 @@ def test_zero_opening_angle_is_the_direct_kernel(sc):
     d, _ = sc.steps_cyl_forces_table(pos, m, e, p.L, tab, order=1, potential=False)
     torch.cuda.synchronize()
     err = rel(a.double().cpu().numpy(), d.double().cpu().numpy())
-    assert err.max() <= 2e-6, err.max()
+    # the same pairs summed in another order: both within 1e-5 of FP64
+    print(f"theta=0 vs direct kernel: max {err.max():.2e}")
+    assert err.max() <= 2e-5, err.max()
     n_cells, n_c, n_p = sc.steps_cyl_tree_info(t)
     assert n_c == 0 and n_p == p.N * p.N
     t.close()
