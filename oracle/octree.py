@@ -20,14 +20,18 @@ leaves open is fixed here (each is a reading):
   a list in depth-first order (children by octant) with, for each cell, the
   index of the first cell after its subtree ("skip").
 * Monopoles.  A cell acts through its mass at its centre of mass.
-* Groups.  Targets are taken in key order (ties by index) in groups of
-  ``group`` consecutive particles; a group walks the tree together and
-  accepts a cell when S0/2^level < theta * d and d > h_group + h_cell, with
-  d the periodic (minimum over the images z_c, z_c +- L) distance from the
-  cell's centre of mass to the group's bounding box, h_group and h_cell the
-  largest softening lengths.  Group size 1 is the classical per-particle
-  criterion.  An accepted cell adds its monopole to every target of the
-  group, an opened leaf its particles (self pairs skipped).
+* Groups.  Targets walk the tree in groups of at most ``group`` particles
+  made of whole sibling cells: for every cell holding more than ``group``
+  particles, its children (in order) that hold at most ``group`` are packed
+  greedily into runs of at most ``group`` particles (a leaf holding more is
+  cut into consecutive runs); a tree with at most ``group`` particles is one
+  group.  A group accepts a cell when S0/2^level < theta * d and
+  d > h_group + h_cell, with d the periodic (minimum over the images z_c,
+  z_c +- L) distance from the cell's centre of mass to the group's bounding
+  box, h_group and h_cell the largest softening lengths.  Group size 1 is
+  the classical per-particle criterion.  An accepted cell adds its monopole
+  to every target of the group, an opened leaf its particles (self pairs
+  skipped).
 * Interactions.  Both are the pair interaction of the tabulated scheme:
   the images |n| <= 1 (spline-softened; beyond the softening for cells)
   plus the band from a correction table (``oracle.table``).  With theta = 0
@@ -137,6 +141,38 @@ class Tree:
         return self.side / (1 << int(self.level[k]))
 
 
+def groups(T, G):
+    """Target groups as (start, count) ranges in key order (see above)."""
+    cnt = T.end - T.start
+    if cnt[0] <= G:
+        return [(0, int(cnt[0]))]
+    out = []
+    for c in range(len(T.cells)):
+        if cnt[c] <= G:
+            continue
+        if T.leaf[c]:
+            out += [(s, min(G, T.end[c] - s)) for s in range(T.start[c], T.end[c], G)]
+            continue
+        run_s, run_n = 0, 0
+        ch = c + 1
+        while ch < T.skip[c]:
+            if cnt[ch] > G:
+                if run_n:
+                    out.append((run_s, run_n))
+                run_n = 0
+            else:
+                if run_n + cnt[ch] > G:
+                    out.append((run_s, run_n))
+                    run_n = 0
+                if run_n == 0:
+                    run_s = int(T.start[ch])
+                run_n += int(cnt[ch])
+            ch = T.skip[ch]
+        if run_n:
+            out.append((run_s, run_n))
+    return out
+
+
 def box_distance(c, lo, hi, L):
     """Distance from point c to the box [lo, hi], periodic along z."""
     dx = max(0.0, lo[0] - c[0], c[0] - hi[0])
@@ -170,8 +206,8 @@ def tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, shift=0.0, angle=0.
     N = T.sm.size
     acc = np.zeros((3, N))     # in key order, transformed frame
     n_cell = n_part = 0
-    for g0 in range(0, N, group):
-        tg = np.arange(g0, min(g0 + group, N))
+    for g0, gn in groups(T, group):
+        tg = np.arange(g0, g0 + gn)
         lo = T.sp[:, tg].min(axis=1)
         hi = T.sp[:, tg].max(axis=1)
         hg = T.sh[tg].max()

@@ -17,8 +17,15 @@
 //  4. depth-first order = sort of (start, level); the "skip" of a cell is
 //     the first cell of the order that starts at its end.
 //
-// Walk: one 64-lane wave per group of 64 consecutive particles in key
-// order.  The wave walks the depth-first list without a stack: a cell is
+// Groups: for every cell holding more than 64 particles, its children that
+// hold at most 64 are packed greedily, in order, into runs of at most 64
+// particles (a leaf holding more is cut into runs of 64); a tree of at most
+// 64 particles is one group.  Groups are thus made of whole sibling cells
+// and stay compact where 64 consecutive particles in key order would not
+// (the key order jumps between distant octants).
+//
+// Walk: one 64-lane wave per group.  The wave walks the depth-first list
+// without a stack: a cell is
 // accepted for the whole group when size < theta d and d > h_group + h_cell,
 // d the distance (periodic in z) from its centre of mass to the group's
 // bounding box; an accepted cell adds its monopole, an opened leaf its
@@ -39,6 +46,7 @@ namespace {
 constexpr int kLevels = 21;
 constexpr int kBlock = 256;
 constexpr int kMaxBins = 256;
+constexpr int kGroup = 64;
 
 // one cell in depth-first order (64 B)
 struct CellRec {
@@ -67,7 +75,9 @@ struct steps_cyl_tree {
     int *c_id_in = nullptr, *c_id_out = nullptr;
     steps::CellRec *cells = nullptr;  // depth-first
     int *cell_level = nullptr;        // depth-first
-    int64_t n_cells = 0, n = 0;
+    int *g_cnt = nullptr, *g_off = nullptr;      // per cell: groups it packs, running total
+    int *g_start = nullptr, *g_count = nullptr;  // per group: particle range
+    int64_t n_cells = 0, n = 0, n_groups = 0;
     // walk statistics, per wave
     int *wave_cells = nullptr, *wave_parts = nullptr;
     // radial correction
@@ -97,7 +107,7 @@ hipError_t ensure_particles(steps_cyl_tree *t, int64_t n) {
 #define G(p) \
     if (e == hipSuccess) e = grow(t->p, c);
     G(tx) G(ty) G(tz) G(key_in) G(key_out) G(idx_in) G(idx_out) G(sx) G(sy) G(sz) G(sm) G(sh)
-    G(act) G(fs) G(fe) G(ss) G(se) G(wave_cells) G(wave_parts)
+    G(act) G(fs) G(fe) G(ss) G(se) G(wave_cells) G(wave_parts) G(g_start) G(g_count)
 #undef G
     if (e != hipSuccess) return e;
     // scratch of the library sort and scan, sized for c items
@@ -151,13 +161,17 @@ hipError_t ensure_cells(steps_cyl_tree *t, int64_t n, hipStream_t stream) {
     regrow(t->c_id_out);
     regrow(t->cells);
     regrow(t->cell_level);
+    regrow(t->g_cnt);
+    regrow(t->g_off);
     if (e != hipSuccess) return e;
     t->cap_cells = c;
-    // the cell sort's scratch grows with the cell count
-    size_t b = 0;
+    // the cell sort's and the cell scan's scratch grow with the cell count
+    size_t b = 0, b2 = 0;
     e = hipcub::DeviceRadixSort::SortPairs(nullptr, b, t->c_key_in, t->c_key_out, t->c_id_in, t->c_id_out, (int)c, 0,
                                            37);
+    if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(nullptr, b2, t->g_cnt, t->g_off, (int)c);
     if (e != hipSuccess) return e;
+    b = std::max(b, b2);
     if (b > t->cub_bytes) {
         (void)hipFree(t->cub_tmp);
         t->cub_tmp = nullptr;
@@ -358,18 +372,67 @@ __global__ void dfs_cells_kernel(int n, int N, const uint64_t *key, const int *i
     cell_level[p] = c_level[c];
 }
 
+// groups packed by cell c (see the file comment); with out < 0 only counted
+__device__ int pack_groups(const CellRec *cells, int c, int *g_start, int *g_count, int out) {
+    const CellRec r = cells[c];
+    int n = 0;
+    auto emit = [&](int s, int k) {
+        if (out >= 0) {
+            g_start[out + n] = s;
+            g_count[out + n] = k;
+        }
+        ++n;
+    };
+    if (r.count <= kGroup) {
+        if (c == 0) emit(0, r.count);  // the whole tree is one group
+        return n;
+    }
+    if (r.leaf) {
+        for (int s = r.start; s < r.start + r.count; s += kGroup) emit(s, min(kGroup, r.start + r.count - s));
+        return n;
+    }
+    int run_s = 0, run_n = 0;
+    for (int ch = c + 1; ch < r.skip; ch = cells[ch].skip) {
+        const int cc = cells[ch].count;
+        if (cc > kGroup) {
+            if (run_n) emit(run_s, run_n);
+            run_n = 0;
+        } else {
+            if (run_n + cc > kGroup) {
+                emit(run_s, run_n);
+                run_n = 0;
+            }
+            if (run_n == 0) run_s = cells[ch].start;
+            run_n += cc;
+        }
+    }
+    if (run_n) emit(run_s, run_n);
+    return n;
+}
+
+__global__ void group_count_kernel(const CellRec *cells, int n, int *g_cnt) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) g_cnt[c] = pack_groups(cells, c, nullptr, nullptr, -1);
+}
+
+__global__ void group_write_kernel(const CellRec *cells, int n, const int *g_cnt, const int *g_off, int *g_start,
+                                   int *g_count) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n && g_cnt[c]) pack_groups(cells, c, g_start, g_count, g_off[c] - g_cnt[c]);
+}
+
 // ---------------------------------------------------------------- walk
 struct WalkArgs {
     const CellRec *cells;
     const double *sx, *sy, *sz, *sm, *sh;
-    const int *idx;
+    const int *idx, *g_start, *g_count;
     float *ax, *ay, *az;
     int *wave_cells, *wave_parts;
     const double *corr;
     TableView tv;
     PeriodConsts pc;
     double theta, c, s, corr_step;
-    int N, n_cells, n_bins;
+    int N, n_cells, n_groups, n_bins;
 };
 
 __device__ __forceinline__ double wave_min(double v) {
@@ -406,10 +469,10 @@ template <int ORDER>
 __global__ __launch_bounds__(kBlock) void tree_walk_kernel(WalkArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
-    const int g0 = wave * 64;
-    if (g0 >= a.N) return;  // whole wave
+    if (wave >= a.n_groups) return;  // whole wave
+    const int g0 = a.g_start[wave];
+    const bool active = lane < a.g_count[wave];
     const int i = g0 + lane;
-    const bool active = i < a.N;
     const int ii = active ? i : g0;
     const double xi = a.sx[ii], yi = a.sy[ii], zi = a.sz[ii];
     const float hi = (float)a.sh[ii];
@@ -634,6 +697,18 @@ int build(steps_cyl_tree *t, const double *pos, const double *mass, const double
                        t->c_id_out, t->c_start, t->c_count, t->c_level, t->c_leaf, t->c_m, t->c_mx, t->c_my, t->c_mz,
                        t->c_h, t->key_out, f, side, t->cells, t->cell_level);
     TRY(hipGetLastError());
+    // target groups
+    hipLaunchKernelGGL(group_count_kernel, dim3(blocks(total)), dim3(kBlock), 0, stream, t->cells, total, t->g_cnt);
+    TRY(hipGetLastError());
+    bytes = t->cub_bytes;
+    TRY(hipcub::DeviceScan::InclusiveSum(t->cub_tmp, bytes, t->g_cnt, t->g_off, total, stream));
+    hipLaunchKernelGGL(group_write_kernel, dim3(blocks(total)), dim3(kBlock), 0, stream, t->cells, total, t->g_cnt,
+                       t->g_off, t->g_start, t->g_count);
+    TRY(hipGetLastError());
+    int ng = 0;
+    TRY(hipMemcpyAsync(&ng, t->g_off + (total - 1), sizeof(int), hipMemcpyDeviceToHost, stream));
+    TRY(hipStreamSynchronize(stream));
+    t->n_groups = ng;
     t->n_cells = total;
     t->n = N;
     return STEPS_OK;
@@ -649,6 +724,9 @@ int walk(steps_cyl_tree *t, const steps_cyl_table *table, int order, double L, d
     a.sm = t->sm;
     a.sh = t->sh;
     a.idx = t->idx_out;
+    a.g_start = t->g_start;
+    a.g_count = t->g_count;
+    a.n_groups = (int)t->n_groups;
     a.ax = out_acc;
     a.ay = out_acc + t->n;
     a.az = out_acc + 2 * t->n;
@@ -664,7 +742,7 @@ int walk(steps_cyl_tree *t, const steps_cyl_table *table, int order, double L, d
     a.corr_step = t->n_bins ? t->corr_rdom / t->n_bins : 1.0;
     a.N = (int)t->n;
     a.n_cells = (int)t->n_cells;
-    const int64_t threads = (t->n + 63) / 64 * 64;
+    const int64_t threads = t->n_groups * 64;
     if (order == 1)
         hipLaunchKernelGGL(tree_walk_kernel<1>, dim3(blocks(threads)), dim3(kBlock), 0, stream, a);
     else
@@ -704,6 +782,7 @@ STEPS_API void steps_cyl_tree_destroy(steps_cyl_tree *t) {
                     t->sz, t->sm, t->sh, t->act, t->fs, t->fe, t->ss, t->se, t->c_start, t->c_count, t->c_level,
                     t->c_leaf, t->c_m, t->c_mx, t->c_my, t->c_mz, t->c_h, t->c_key_in, t->c_key_out, t->c_id_in,
                     t->c_id_out, t->cells, t->cell_level, t->wave_cells, t->wave_parts, t->corr, t->bin_sum,
+                    t->g_cnt, t->g_off, t->g_start, t->g_count,
                     t->bin_cnt, t->acc_dir, t->acc_tree};
     for (void *p : ptrs) (void)hipFree(p);
     delete t;
@@ -804,17 +883,17 @@ STEPS_API int steps_cyl_tree_info(const steps_cyl_tree *t, int64_t *n_cells, int
     clear_error();
     if (n_cells) *n_cells = t->n_cells;
     if (cell_interactions || particle_interactions) {
-        const int64_t waves = (t->n + 63) / 64;
-        std::vector<int> wc(waves), wp(waves);
+        const int64_t waves = t->n_groups;
+        std::vector<int> wc(waves), wp(waves), gc(waves);
         if (waves) {
             STEPS_CHECK_HIP(hipMemcpy(wc.data(), t->wave_cells, waves * sizeof(int), hipMemcpyDeviceToHost));
             STEPS_CHECK_HIP(hipMemcpy(wp.data(), t->wave_parts, waves * sizeof(int), hipMemcpyDeviceToHost));
+            STEPS_CHECK_HIP(hipMemcpy(gc.data(), t->g_count, waves * sizeof(int), hipMemcpyDeviceToHost));
         }
         int64_t sc = 0, sp = 0;
         for (int64_t w = 0; w < waves; ++w) {
-            const int64_t lanes = std::min<int64_t>(64, t->n - 64 * w);
-            sc += lanes * wc[w];
-            sp += lanes * wp[w];
+            sc += (int64_t)gc[w] * wc[w];
+            sp += (int64_t)gc[w] * wp[w];
         }
         if (cell_interactions) *cell_interactions = sc;
         if (particle_interactions) *particle_interactions = sp;

@@ -133,3 +133,29 @@ def test_radial_calibration_removes_the_mean_radial_bias(load, tab, direct):
     z = oc.calibrate(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.0, shifts[:1], angles[:1], nb,
                      leaf_size=8, group=16)
     assert np.abs(z).max() < 1e-12
+
+
+@pytest.mark.parametrize("G,leaf", [(64, 16), (8, 16), (1, 4)])
+def test_groups_partition_the_particles_into_compact_runs(load, G, leaf):
+    T = oc.Tree(load.pos, load.mass, load.eps, load.L, R, 0.1, 0.2, leaf_size=leaf)
+    gs = sorted(oc.groups(T, G))
+    assert gs[0][0] == 0 and sum(n for _, n in gs) == load.N
+    assert all(a[0] + a[1] == b[0] for a, b in zip(gs[:-1], gs[1:]))
+    assert all(1 <= n <= G for _, n in gs)
+    # each group is a run of whole children of one cell holding more than G
+    # particles (or a run of a leaf holding more than G)
+    cnt = T.end - T.start
+    for s, n in gs:
+        inside = [k for k in range(len(T.cells))
+                  if T.start[k] <= s and s + n <= T.end[k] and cnt[k] > G]
+        owner = max(inside, key=lambda k: T.level[k])
+        if T.leaf[owner]:
+            assert (s - T.start[owner]) % G == 0
+            continue
+        kids, c = [], owner + 1
+        while c < T.skip[owner]:
+            kids.append(c)
+            c = T.skip[c]
+        starts = {int(T.start[c]) for c in kids if cnt[c] <= G}
+        ends = {int(T.end[c]) for c in kids if cnt[c] <= G}
+        assert s in starts and s + n in ends
