@@ -397,7 +397,8 @@ typedef struct {
     double a_begin, a_end;   /* scale factor at the start and the end of the step (> 0)   */
     double H0;               /* Hubble constant in code units (G = 1), > 0                */
     double Omega_m, Omega_L, Omega_r, Omega_k, w0, wa;  /* density parameters, CPL w(a)   */
-    double R_cyl, rho0;      /* compensated cylinder: radius and comoving density          */
+    double R_cyl, rho0;      /* compensated cylinder: radius and comoving density; R_cyl
+                                also bounds the particles' radius for a tree (R_dom)       */
     int compensate;          /* 1: subtract F_h; 0: pair forces only                        */
     int n_img;               /* exact images when net == NULL                               */
     const steps_cyl_mlp *net;  /* learned correction, or NULL for the exact sum            */
@@ -406,6 +407,10 @@ typedef struct {
                                 the background fields are then not used             */
     const steps_cyl_table *table;  /* tabulated correction (net must be NULL), or NULL   */
     int table_order;         /* 1 = CIC, 2 = TSC, with a table                              */
+    steps_cyl_tree *tree;    /* octree forces over `table` (which must be given), or NULL   */
+    double theta;            /* opening angle, with a tree                                  */
+    double tree_shift, tree_angle;  /* the step's random frame (caller's draws)            */
+    int tree_correct;        /* 1: subtract the tree's radial correction                    */
 } steps_cyl_kdk_params;
 
 /* Kick and drift factors of one step (host only, no device work):

@@ -81,6 +81,8 @@ class KdkParams(ctypes.Structure):
         ("R_cyl", ctypes.c_double), ("rho0", ctypes.c_double),
         ("compensate", ctypes.c_int), ("n_img", ctypes.c_int), ("net", ctypes.c_void_p),
         ("factors", ctypes.c_void_p), ("table", ctypes.c_void_p), ("table_order", ctypes.c_int),
+        ("tree", ctypes.c_void_p), ("theta", ctypes.c_double), ("tree_shift", ctypes.c_double),
+        ("tree_angle", ctypes.c_double), ("tree_correct", ctypes.c_int),
     ]
 
 
@@ -442,7 +444,7 @@ _FACTOR_KEEP = []
 
 def kdk_params(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r=0.0, Omega_k=0.0, w0=-1.0, wa=0.0,
                R_cyl=1.0, rho0=0.0, compensate=True, n_img=8, net=None, factors=None, table=None,
-               table_order=2):
+               table_order=2, tree=None, theta=0.5, tree_shift=0.0, tree_angle=0.0, tree_correct=False):
     fp = None
     if factors is not None:
         arr = (ctypes.c_double * 3)(*[float(x) for x in factors])
@@ -452,7 +454,9 @@ def kdk_params(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r=0.0, Omega_k=0.0, w
     return KdkParams(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r, Omega_k, w0, wa, R_cyl, rho0,
                      1 if compensate else 0, int(n_img), _handle(net) if net is not None else None,
                      fp, (table.handle if isinstance(table, CorrectionTable) else table) if table is not None
-                     else None, int(table_order))
+                     else None, int(table_order),
+                     (tree.handle if isinstance(tree, Octree) else tree) if tree is not None else None,
+                     float(theta), float(tree_shift), float(tree_angle), 1 if tree_correct else 0)
 
 
 def steps_cyl_history_factors(t, a, order, a_begin, a_end):

@@ -221,6 +221,10 @@ int check_force_params(const steps_cyl_kdk_params *p) {
     if (p->compensate && (!finite_positive(p->R_cyl) || !std::isfinite(p->rho0) || p->rho0 < 0.0))
         return fail(STEPS_EINVAL, "compensation needs R_cyl > 0 and rho0 >= 0");
     if (p->net && p->table) return fail(STEPS_EINVAL, "give a network or a table, not both");
+    if (p->tree && !p->table) return fail(STEPS_EINVAL, "a tree needs a table");
+    if (p->tree && (!std::isfinite(p->theta) || p->theta < 0.0 || !std::isfinite(p->tree_shift) ||
+                    !std::isfinite(p->tree_angle)))
+        return fail(STEPS_EINVAL, "tree: theta >= 0, shift and angle finite");
     if (p->table && p->table_order != 1 && p->table_order != 2)
         return fail(STEPS_EINVAL, "table_order=%d: 1 (CIC) or 2 (TSC)", p->table_order);
     if (!p->net && !p->table && (p->n_img < 0 || p->n_img > STEPS_MAX_NIMG))
@@ -414,6 +418,10 @@ STEPS_API int steps_cyl_kdk_step(double *pos, double *mom, const double *mass, c
     if (params->net)
         rc = launch_forces_learned(pos, mass, eps, N, L, params->net, nullptr, N, STEPS_SUM_COMPENSATED,
                                    acc_inout, nullptr, stream);
+    else if (params->tree)
+        rc = steps_cyl_tree_forces(params->tree, pos, mass, eps, N, L, params->R_cyl, params->table,
+                                   params->table_order, params->theta, params->tree_shift, params->tree_angle,
+                                   params->tree_correct, acc_inout, stream);
     else if (params->table)
         rc = steps_cyl_forces_table(pos, mass, eps, N, L, params->table, params->table_order, nullptr, N,
                                     acc_inout, nullptr, stream);

@@ -7,10 +7,12 @@ density (H0^2 = 8 pi G rho0 / (3 Omega_m)), and steps uniform in ln a.  Forces
 are the learned correction (exact |n| <= 1 + network), the exact sum with
 |n| <= n_img, the interpolated table of the band 2 <= |n| <= 1024 (Sect. 2.2)
 or the complete table of every image (N_cut -> infinity, from the Ewald
-split); the homogeneous-cylinder pull of the matching height is compensated.
+split), or the octree over the complete table (Sect. 2.4: a random shift and
+rotation of the domain per step, radial correction calibrated on the initial
+load); the homogeneous-cylinder pull of the matching height is compensated.
 Every --check-every steps the axial momentum and the force error on sampled
 targets against the FP64 GPU reference (|n| <= 1024 for the learned and band
-modes, n_img for exact, 4096 for complete) are reported.  Prints one line
+modes, n_img for exact, 4096 for complete and tree) are reported.  Prints one line
 per step and a JSON summary.
 
     python -m paper_2602_20787_amd.simulate --N 131072 --steps 64
@@ -37,7 +39,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--a0", type=float, default=0.02)
     ap.add_argument("--a1", type=float, default=1.0)
-    ap.add_argument("--mode", choices=["learned", "exact", "table", "complete"], default="learned")
+    ap.add_argument("--mode", choices=["learned", "exact", "table", "complete", "tree"], default="learned")
+    ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--table-order", type=int, choices=[1, 2], default=2)
     ap.add_argument("--n-img", type=int, default=8)
     ap.add_argument("--check-every", type=int, default=8)
@@ -67,13 +70,23 @@ def main(argv=None):
     table = None
     if args.mode == "table":
         table = sc.CorrectionTable(128, 144, 6.4, 1024)
-    elif args.mode == "complete":
+    elif args.mode in ("complete", "tree"):
         table = sc.CorrectionTable.ewald(128, 144, 6.4, 2.0, 5, 12)
-    truth_img = {"learned": 1024, "table": 1024, "complete": 4096}.get(args.mode, args.n_img)
+    truth_img = {"learned": 1024, "table": 1024, "complete": 4096, "tree": 4096}.get(args.mode, args.n_img)
+    tree = None
+    frames = np.random.default_rng(args.seed + 17)
+    if args.mode == "tree":
+        tree = sc.Octree(16)
+        corr = sc.steps_cyl_tree_calibrate(tree, pos, m, e, L, R, table, args.table_order, args.theta,
+                                           frames.random(4) * L, frames.random(4) * 2 * math.pi, 32)
+        print(f"[sim] radial correction calibrated: max |dF_rho| {np.abs(corr).max():.2e}", flush=True)
 
     def forces():
         if net is not None:
             a, _ = sc.steps_cyl_forces_learned(pos, m, e, L, net, potential=False)
+        elif tree is not None:
+            a = sc.steps_cyl_tree_forces(tree, pos, m, e, L, R, table, args.table_order, args.theta,
+                                         frames.random() * L, frames.random() * 2 * math.pi, correct=True)
         elif table is not None:
             a, _ = sc.steps_cyl_forces_table(pos, m, e, L, table, order=args.table_order, potential=False)
         else:
@@ -103,7 +116,9 @@ def main(argv=None):
     pz_max_ratio = 0.0
     for k in range(args.steps):
         par = sc.kdk_params(grid[k], grid[k + 1], H0, Om, OL, R_cyl=R, rho0=rho0,
-                            n_img=args.n_img, net=net, table=table, table_order=args.table_order)
+                            n_img=args.n_img, net=net, table=table, table_order=args.table_order,
+                            tree=tree, theta=args.theta, tree_shift=frames.random() * L,
+                            tree_angle=frames.random() * 2 * math.pi, tree_correct=tree is not None)
         sc.steps_cyl_kdk_step(pos, mom, m, e, L, par, acc)
         torch.cuda.synchronize()
         P, Ps = pz()
@@ -129,6 +144,8 @@ def main(argv=None):
     print(json.dumps(summary), flush=True)
     if net is not None:
         net.close()
+    if tree is not None:
+        tree.close()
     if table is not None:
         table.close()
     return 0

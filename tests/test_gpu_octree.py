@@ -173,3 +173,40 @@ def test_force_error_statistics_follow_the_opening_angle(sc):
     for r in rows[1:]:
         assert abs(r[6] - 1) <= abs(r[3] - 1) + 1e-4
     tab.close()
+
+
+def test_kdk_step_with_octree_composes_its_parts(sc):
+    # one step with octree forces over a complete table and the step's random
+    # frame: the force at the drifted positions is the tree force there (the
+    # build and walk are deterministic), and the momenta are the two kicks
+    # with the infinite cylinder's pull.  The parts are each checked against
+    # the oracle elsewhere; comparing the drifted state with the oracle would
+    # let FP32-level position differences move particles across cell faces.
+    p = synth.displaced_load(900, seed=38)
+    rho0 = 1.0 / (math.pi * R * R * p.L)
+    H0 = math.sqrt(8 * math.pi * rho0 / 0.9)
+    t = sc.Octree(16)
+    tab = sc.CorrectionTable.ewald(24, 16, 4.0, 2.0, 5, 12)
+    theta, s0, a0, s1, a1 = 0.6, 0.1, 0.4, 0.7, 2.9
+    pos, m, e = to_dev(p)
+    pos0 = pos.clone()
+    acc0 = sc.steps_cyl_tree_forces(t, pos, m, e, p.L, R, tab, 1, theta, s0, a0)
+    acc = acc0.clone()
+    mom = torch.zeros_like(pos)
+    par = sc.kdk_params(0.05, 0.06, H0, 0.3, 0.7, R_cyl=R, rho0=rho0, table=tab, table_order=1,
+                        tree=t, theta=theta, tree_shift=s1, tree_angle=a1)
+    sc.steps_cyl_kdk_step(pos, mom, m, e, p.L, par, acc)
+    acc1 = sc.steps_cyl_tree_forces(t, pos, m, e, p.L, R, tab, 1, theta, s1, a1)
+    torch.cuda.synchronize()
+    assert torch.equal(acc, acc1)
+    K1, D, K2 = sc.steps_cyl_kdk_factors(par)
+    c0 = sc.steps_cyl_compensation(pos0, R, math.inf, rho0)
+    c1 = sc.steps_cyl_compensation(pos, R, math.inf, rho0)
+    mid = K1 * (acc0.double() - c0)
+    expect = mid + K2 * (acc1.double() - c1)
+    torch.testing.assert_close(mom, expect, rtol=1e-12, atol=1e-15)
+    dx = pos - pos0 - D * mid
+    dx[2] -= torch.round(dx[2] / p.L) * p.L
+    assert float(dx.abs().max()) < 1e-12
+    t.close()
+    tab.close()

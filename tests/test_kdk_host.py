@@ -116,3 +116,16 @@ def test_table_settings_are_checked():
     assert e.value.code == sc.STEPS_EINVAL
     # with a table n_img is not used
     sc.steps_cyl_kdk_factors(sc.kdk_params(**base, table=fake, table_order=1, n_img=-5))
+
+
+def test_tree_settings_are_checked():
+    fake = 0x1000
+    base = dict(a_begin=0.1, a_end=0.2, H0=1.0, Omega_m=0.3, Omega_L=0.7)
+    with pytest.raises(sc.StepsError) as e:
+        sc.steps_cyl_kdk_factors(sc.kdk_params(**base, tree=fake))
+    assert "needs a table" in str(e.value)
+    with pytest.raises(sc.StepsError):
+        sc.steps_cyl_kdk_factors(sc.kdk_params(**base, tree=fake, table=fake, theta=-1.0))
+    with pytest.raises(sc.StepsError):
+        sc.steps_cyl_kdk_factors(sc.kdk_params(**base, tree=fake, table=fake, tree_angle=float("inf")))
+    sc.steps_cyl_kdk_factors(sc.kdk_params(**base, tree=fake, table=fake, theta=0.5))
