@@ -50,7 +50,9 @@ __device__ __forceinline__ void pair_fast(float dx, float dy, float d, const Ima
     const float rho2 = __builtin_fmaf(dx, dx, dy * dy);
     const float r2_0 = __builtin_fmaf(d, d, rho2);
     const float ri0 = __builtin_amdgcn_rsqf(r2_0);
-    float Tp = 0.f, Tm = 0.f, Up = 0.f, Um = 0.f, Pp = 0.f, Pm = 0.f;
+    // the sums start at -0: x + (-0) = x for every x, so the first additions
+    // fold away (a +0 start would cost an add per sum: +0 + -0 is +0, not -0)
+    float Tp = -0.f, Tm = -0.f, Up = -0.f, Um = -0.f, Pp = -0.f, Pm = -0.f;
     if (n_img >= 2) {
         const float B = d * c.m2Lf;  // -2 L d
 #pragma unroll
