@@ -199,14 +199,22 @@ def _interact(tree, tg, src_pos, src_m, src_h, src_id, tab, order, acc):
 
 
 def tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, shift=0.0, angle=0.0,
-                leaf_size=16, group=64, stats=None):
+                leaf_size=16, group=64, stats=None, targets=None):
     """Accelerations (3, N) of every particle by the octree (G = 1), in the
-    original frame and order."""
+    original frame and order; with ``targets`` (original indices) only the
+    groups holding them are walked and (3, len(targets)) is returned."""
     T = Tree(pos, mass, eps, L, R_dom, shift, angle, leaf_size)
     N = T.sm.size
     acc = np.zeros((3, N))     # in key order, transformed frame
     n_cell = n_part = 0
-    for g0, gn in groups(T, group):
+    gl = groups(T, group)
+    if targets is not None:
+        where = np.empty(N, dtype=np.int64)
+        where[T.order] = np.arange(N)            # key-order position of each particle
+        starts = np.array([g[0] for g in gl])
+        keep = np.unique(np.searchsorted(starts, where[np.asarray(targets)], side="right") - 1)
+        gl = [gl[k] for k in keep]
+    for g0, gn in gl:
         tg = np.arange(g0, g0 + gn)
         lo = T.sp[:, tg].min(axis=1)
         hi = T.sp[:, tg].max(axis=1)
@@ -233,7 +241,8 @@ def tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, shift=0.0, angle=0.
     c, s = math.cos(angle), math.sin(angle)
     ax = c * out[0] + s * out[1]
     ay = -s * out[0] + c * out[1]
-    return np.stack([ax, ay, out[2]])
+    res = np.stack([ax, ay, out[2]])
+    return res if targets is None else res[:, np.asarray(targets)]
 
 
 # ---------------------------------------------------------------- radial correction

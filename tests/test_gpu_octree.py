@@ -210,3 +210,22 @@ def test_kdk_step_with_octree_composes_its_parts(sc):
     assert float(dx.abs().max()) < 1e-12
     t.close()
     tab.close()
+
+
+def test_full_size_sampled_matches_oracle(sc):
+    # the benchmark's size: N = 2^20, theta = 0.5, 144 x 128 band table; the
+    # oracle walks only the groups holding the sampled targets
+    N = 1 << 20
+    p = synth.cylinder_load(N, seed=0)
+    t = sc.Octree(16)
+    tab = sc.CorrectionTable(128, 144, 6.4, 1024)
+    a = sc.steps_cyl_tree_forces(t, *to_dev(p), p.L, R, tab, 1, 0.5, 0.25, 1.7)
+    torch.cuda.synchronize()
+    tg = synth.target_sample(N, 12, seed=51)
+    ref = oc.tree_forces(p.pos, p.mass, p.eps, p.L, R, ot.Table(128, 144, 6.4), 1, 0.5, 0.25, 1.7,
+                         targets=tg)
+    err = rel(a[:, torch.from_numpy(tg).cuda()].double().cpu().numpy(), ref)
+    print(f"N=2^20 theta=0.5: max rel err vs oracle {err.max():.2e} on {tg.size} targets")
+    assert err.max() <= 2e-5
+    t.close()
+    tab.close()

@@ -80,3 +80,20 @@ def test_table_accuracy_against_exact_1024(sc):
     print(f"|n|<=8: max {e8.max():.3e}")
     assert out[1].max() < 0.05 * e8.max() and out[2].max() < 0.05 * e8.max()
     t.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_table_full_size_sampled_matches_oracle(sc, order):
+    # the benchmark's size and grid: N = 2^20, 144 x 128, on sampled targets
+    N = 1 << 20
+    p = synth.cylinder_load(N, seed=0)
+    t = sc.CorrectionTable(128, 144, 6.4, 1024)
+    tg = synth.target_sample(N, 24, seed=52)
+    pos, m, e = to_dev(p)
+    a, _ = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order, targets=torch.from_numpy(tg).cuda(),
+                                     potential=False)
+    ref = ot.forces_table(p.pos, p.mass, p.eps, p.L, ot.Table(128, 144, 6.4), order, targets=tg)
+    err = rel(a, ref)
+    print(f"order {order}, N=2^20: max rel err vs oracle {err.max():.2e}")
+    assert err.max() <= 2e-5
+    t.close()
