@@ -311,18 +311,19 @@ int steps_cyl_forces_table(const double *pos, const double *mass, const double *
  * it (z wrapped into [0, L)); R_dom must bound the particles' radius.  Cells
  * are split while they hold more than leaf_size particles (down to level
  * 21); each acts through its mass at its centre of mass.  Particles are
- * taken in Morton order in groups of 64 that walk the tree together: a cell
- * is accepted for a group when S0/2^level < theta d and
- * d > h_group + h_cell, with d the distance (periodic in z) from the cell's
- * centre of mass to the group's bounding box and h the largest softening
- * lengths; otherwise it is opened, and an opened leaf contributes its
- * particles.  Cells and particles interact through the pair of the tabulated
- * scheme (exact images |n| <= 1, softened, plus the table's band), so
- * theta = 0 gives steps_cyl_forces_table's forces.
+ * grouped for the walk into runs of at most 64 made of whole sibling cells
+ * (children of a cell holding more than 64, packed in order); a group walks
+ * the tree together and accepts a cell when (S0/2^level)^2 < theta^2 d^2 and
+ * d^2 > (h_group + h_cell)^2, with d the distance (periodic in z) from the
+ * cell's centre of mass to the group's bounding box and h the largest
+ * softening lengths; otherwise the cell is opened, and an opened leaf
+ * contributes its particles.  Cells and particles interact through the pair
+ * of the tabulated scheme (exact images |n| <= 1, softened, plus the
+ * table's band), so theta = 0 gives steps_cyl_forces_table's forces.
  *
- * The tree object owns its device buffers (sized on first use and grown
- * when N grows; the build and the walk allocate nothing else) and the radial
- * correction.  Calls on one tree must not overlap.
+ * The tree object owns its device buffers (sized on first use, grown when
+ * N or the cell count outgrows them; nothing else is allocated) and the
+ * radial correction.  Calls on one tree must not overlap.
  * ---------------------------------------------------------------------- */
 typedef struct steps_cyl_tree steps_cyl_tree;   /* opaque */
 

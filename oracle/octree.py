@@ -25,10 +25,11 @@ leaves open is fixed here (each is a reading):
   particles, its children (in order) that hold at most ``group`` are packed
   greedily into runs of at most ``group`` particles (a leaf holding more is
   cut into consecutive runs); a tree with at most ``group`` particles is one
-  group.  A group accepts a cell when S0/2^level < theta * d and
-  d > h_group + h_cell, with d the periodic (minimum over the images z_c,
-  z_c +- L) distance from the cell's centre of mass to the group's bounding
-  box, h_group and h_cell the largest softening lengths.  Group size 1 is
+  group.  A group accepts a cell when (S0/2^level)^2 < theta^2 d^2 and
+  d^2 > (h_group + h_cell)^2 (compared squared, as written), with d the
+  periodic (minimum over the images z_c, z_c +- L) distance from the cell's
+  centre of mass to the group's bounding box, h_group and h_cell the largest
+  softening lengths.  Group size 1 is
   the classical per-particle criterion.  An accepted cell adds its monopole
   to every target of the group, an opened leaf its particles (self pairs
   skipped).
@@ -173,12 +174,12 @@ def groups(T, G):
     return out
 
 
-def box_distance(c, lo, hi, L):
-    """Distance from point c to the box [lo, hi], periodic along z."""
+def box_distance2(c, lo, hi, L):
+    """Squared distance from point c to the box [lo, hi], periodic along z."""
     dx = max(0.0, lo[0] - c[0], c[0] - hi[0])
     dy = max(0.0, lo[1] - c[1], c[1] - hi[1])
     dz = min(max(0.0, lo[2] - cz, cz - hi[2]) for cz in (c[2] - L, c[2], c[2] + L))
-    return math.sqrt(dx * dx + dy * dy + dz * dz)
+    return dx * dx + dy * dy + dz * dz
 
 
 def _interact(tree, tg, src_pos, src_m, src_h, src_id, tab, order, acc):
@@ -220,9 +221,11 @@ def tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, shift=0.0, angle=0.
         hi = T.sp[:, tg].max(axis=1)
         hg = T.sh[tg].max()
         k = 0
+        theta2 = theta * theta
         while k < len(T.cells):
-            d = box_distance(T.com[:, k], lo, hi, L)
-            if T.size(k) < theta * d and d > hg + T.hmax[k]:
+            d2 = box_distance2(T.com[:, k], lo, hi, L)
+            hs = hg + T.hmax[k]
+            if T.size(k) * T.size(k) < theta2 * d2 and d2 > hs * hs:
                 _interact(T, tg, T.com[:, k:k + 1], T.mass[k:k + 1], T.hmax[k:k + 1],
                           np.array([-1]), tab, order, acc)
                 n_cell += tg.size

@@ -26,7 +26,8 @@
 //
 // Walk: one 64-lane wave per group.  The wave walks the depth-first list
 // without a stack: a cell is
-// accepted for the whole group when size < theta d and d > h_group + h_cell,
+// accepted for the whole group when size^2 < theta^2 d^2 and
+// d^2 > (h_group + h_cell)^2,
 // d the distance (periodic in z) from its centre of mass to the group's
 // bounding box; an accepted cell adds its monopole, an opened leaf its
 // particles, both through the pair interaction of the tabulated scheme
@@ -431,7 +432,7 @@ struct WalkArgs {
     const double *corr;
     TableView tv;
     PeriodConsts pc;
-    double theta, c, s, corr_step;
+    double theta2, c, s, corr_step;
     int N, n_cells, n_groups, n_bins;
 };
 
@@ -444,9 +445,10 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// distance from c to the box [lo, hi], periodic along z (no contraction,
-// so that the acceptance decisions round as written)
-__device__ double box_distance(double cx, double cy, double cz, const double lo[3], const double hi[3], double L) {
+// squared distance from c to the box [lo, hi], periodic along z (no
+// contraction, so that the acceptance decisions round as written)
+__device__ double box_distance2(double cx, double cy, double cz, const double lo[3], const double hi[3],
+                                double L) {
 #pragma clang fp contract(off)
     const double dx = fmax(0.0, fmax(lo[0] - cx, cx - hi[0]));
     const double dy = fmax(0.0, fmax(lo[1] - cy, cy - hi[1]));
@@ -455,14 +457,16 @@ __device__ double box_distance(double cx, double cy, double cz, const double lo[
         const double z = cz + k * L;
         dz = fmin(dz, fmax(0.0, fmax(lo[2] - z, z - hi[2])));
     }
-    return sqrt(dx * dx + dy * dy + dz * dz);
+    return dx * dx + dy * dy + dz * dz;
 }
 
-__device__ bool accept_cell(const CellRec &r, const double lo[3], const double hi[3], double hg, double theta,
+// size^2 < theta^2 d^2 and d^2 > (h_group + h_cell)^2, compared squared
+__device__ bool accept_cell(const CellRec &r, const double lo[3], const double hi[3], double hg, double theta2,
                             double L) {
 #pragma clang fp contract(off)
-    const double d = box_distance(r.cx, r.cy, r.cz, lo, hi, L);
-    return r.size < theta * d && d > hg + r.hmax;
+    const double d2 = box_distance2(r.cx, r.cy, r.cz, lo, hi, L);
+    const double hs = hg + r.hmax;
+    return r.size * r.size < theta2 * d2 && d2 > hs * hs;
 }
 
 template <int ORDER>
@@ -486,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void tree_walk_kernel(WalkArgs a) {
     while (p < a.n_cells) {
         const CellRec r = a.cells[p];
         // every lane evaluates the same FP64 test on the same data
-        const int acc = __builtin_amdgcn_readfirstlane(accept_cell(r, lo, up, hg, a.theta, a.pc.L) ? 1 : 0);
+        const int acc = __builtin_amdgcn_readfirstlane(accept_cell(r, lo, up, hg, a.theta2, a.pc.L) ? 1 : 0);
         if (acc) {
             SrcRec src;
             src.x = r.cx;
@@ -735,7 +739,7 @@ int walk(steps_cyl_tree *t, const steps_cyl_table *table, int order, double L, d
     a.corr = t->corr;
     a.tv = table_view(table);
     a.pc = period_consts(L);
-    a.theta = theta;
+    a.theta2 = theta * theta;
     a.c = f.c;
     a.s = f.s;
     a.n_bins = correct ? t->n_bins : 0;
