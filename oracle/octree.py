@@ -208,7 +208,7 @@ def tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, shift=0.0, angle=0.
     N = T.sm.size
     acc = np.zeros((3, N))     # in key order, transformed frame
     n_cell = n_part = 0
-    gl = groups(T, group)
+    gl = sorted(groups(T, group))             # by start (cells emit them in depth-first order)
     if targets is not None:
         where = np.empty(N, dtype=np.int64)
         where[T.order] = np.arange(N)            # key-order position of each particle

@@ -112,14 +112,11 @@ hipError_t ensure_particles(steps_cyl_tree *t, int64_t n) {
 #undef G
     if (e != hipSuccess) return e;
     // scratch of the library sort and scan, sized for c items
-    size_t b1 = 0, b2 = 0, b3 = 0;
+    size_t b1 = 0, b2 = 0;
     e = hipcub::DeviceRadixSort::SortPairs(nullptr, b1, t->key_in, t->key_out, t->idx_in, t->idx_out, (int)c, 0, 63);
     if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(nullptr, b2, t->fs, t->ss, (int)c);
-    if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(nullptr, b3, t->c_key_in, t->c_key_out, t->c_id_in, t->c_id_out,
-                                               (int)(2 * c), 0, 37);
     if (e != hipSuccess) return e;
-    const size_t need = std::max(b1, std::max(b2, b3));
+    const size_t need = std::max(b1, b2);
     if (need > t->cub_bytes) {
         (void)hipFree(t->cub_tmp);
         t->cub_tmp = nullptr;
@@ -660,6 +657,8 @@ int build(steps_cyl_tree *t, const double *pos, const double *mass, const double
         TRY(hipMemcpyAsync(&m, t->ss + (n - 1), sizeof(int), hipMemcpyDeviceToHost, stream));
         TRY(hipStreamSynchronize(stream));
         if (m == 0) break;
+        if ((int64_t)total + m > ((int64_t)1 << 30))
+            return fail(STEPS_EINVAL, "more than 2^30 tree cells (coincident particles?)");
         TRY(ensure_cells(t, (int64_t)total + m, stream));
         hipLaunchKernelGGL(compact_kernel, dim3(blocks(N)), dim3(kBlock), 0, stream, t->fs, t->fe, t->ss, t->se, n,
                            total, t->c_start, t->c_count);

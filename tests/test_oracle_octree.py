@@ -159,3 +159,12 @@ def test_groups_partition_the_particles_into_compact_runs(load, G, leaf):
         starts = {int(T.start[c]) for c in kids if cnt[c] <= G}
         ends = {int(T.end[c]) for c in kids if cnt[c] <= G}
         assert s in starts and s + n in ends
+
+
+def test_target_subset_walks_the_same_groups(load, tab):
+    tg = np.array([0, 5, 77, 311, 699])
+    full = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.5, 0.25, 1.7,
+                          leaf_size=8, group=16)
+    sub = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.5, 0.25, 1.7,
+                         leaf_size=8, group=16, targets=tg)
+    np.testing.assert_array_equal(sub, full[:, tg])
