@@ -439,24 +439,21 @@ def steps_cyl_forces_learned_ex(pos, mass, eps, L, net, targets=None, mode=STEPS
 
 
 # ---------------------------------------------------------------- time integration
-_FACTOR_KEEP = []
-
-
 def kdk_params(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r=0.0, Omega_k=0.0, w0=-1.0, wa=0.0,
                R_cyl=1.0, rho0=0.0, compensate=True, n_img=8, net=None, factors=None, table=None,
                table_order=2, tree=None, theta=0.5, tree_shift=0.0, tree_angle=0.0, tree_correct=False):
-    fp = None
+    arr = None
     if factors is not None:
         arr = (ctypes.c_double * 3)(*[float(x) for x in factors])
-        _FACTOR_KEEP.append(arr)
-        del _FACTOR_KEEP[:-64]
-        fp = ctypes.cast(arr, ctypes.c_void_p)
-    return KdkParams(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r, Omega_k, w0, wa, R_cyl, rho0,
-                     1 if compensate else 0, int(n_img), _handle(net) if net is not None else None,
-                     fp, (table.handle if isinstance(table, CorrectionTable) else table) if table is not None
-                     else None, int(table_order),
-                     (tree.handle if isinstance(tree, Octree) else tree) if tree is not None else None,
-                     float(theta), float(tree_shift), float(tree_angle), 1 if tree_correct else 0)
+    p = KdkParams(a_begin, a_end, H0, Omega_m, Omega_L, Omega_r, Omega_k, w0, wa, R_cyl, rho0,
+                  1 if compensate else 0, int(n_img), _handle(net) if net is not None else None,
+                  ctypes.cast(arr, ctypes.c_void_p) if arr is not None else None,
+                  (table.handle if isinstance(table, CorrectionTable) else table) if table is not None
+                  else None, int(table_order),
+                  (tree.handle if isinstance(tree, Octree) else tree) if tree is not None else None,
+                  float(theta), float(tree_shift), float(tree_angle), 1 if tree_correct else 0)
+    p._factors = arr   # the struct points into it: keep it alive as long as the struct
+    return p
 
 
 def steps_cyl_history_factors(t, a, order, a_begin, a_end):

@@ -1,0 +1,36 @@
+"""The simulation driver runs every force mode end to end on a small load:
+a few KDK steps from a = 0.02, axial momentum and force-error checks against
+the FP64 GPU reference.  Bars per mode: the force error of the mode at the
+last check (exact |n| <= 8: round-off; learned: network error; table and
+complete: interpolation error; tree: opening-angle error) and the axial
+momentum (conserved pair by pair except by the tree)."""
+import json
+
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sim():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_20787_amd import simulate
+    return simulate
+
+
+@pytest.mark.parametrize("mode,err,pz", [("exact", 2e-5, 1e-7), ("learned", 1e-4, 1e-7),
+                                         ("table", 2e-3, 1e-7), ("complete", 2e-3, 1e-7),
+                                         ("tree", 0.3, 1e-2)])
+def test_driver_runs_each_mode(sim, capsys, mode, err, pz):
+    rc = sim.main(["--N", "4096", "--steps", "4", "--mode", mode, "--check-every", "4",
+                   "--check-targets", "256", "--a1", "0.05"])
+    assert rc == 0
+    out = capsys.readouterr().out.strip().splitlines()
+    summary = json.loads(out[-1])
+    assert summary["mode"] == mode and summary["steps"] == 4
+    last = summary["checks"][-1]
+    print(mode, last, summary["max_pz_ratio"])
+    assert last["max_rel_err"] <= err
+    assert summary["max_pz_ratio"] <= pz
