@@ -229,3 +229,39 @@ def test_full_size_sampled_matches_oracle(sc):
     assert err.max() <= 2e-5
     t.close()
     tab.close()
+
+
+@pytest.mark.parametrize("case", ["one", "two", "coincident", "outside"])
+def test_edge_cases_match_oracle(sc, case):
+    rng = np.random.default_rng(61)
+    if case == "one":
+        p = synth.cylinder_load(1, seed=62)
+    elif case == "two":
+        p = synth.cylinder_load(2, seed=63)
+    else:
+        base = synth.cylinder_load(300, seed=64)
+        pos = base.pos.copy()
+        if case == "coincident":
+            pos[:, :100] = pos[:, [7]]          # 100 particles on one point: a level-21 leaf
+        else:
+            pos[0, :5] = 2.0 * R * (1 + rng.random(5))   # beyond the root cube: clamped cells
+        p = synth.Particles(pos, base.mass, base.eps, base.L)
+    t = sc.Octree(4)
+    tab = sc.CorrectionTable(24, 16, 20.0, 1024)
+    a = sc.steps_cyl_tree_forces(t, *to_dev(p), p.L, R, tab, 1, 0.6, 0.3, 0.9)
+    torch.cuda.synchronize()
+    st = {}
+    ref = oc.tree_forces(p.pos, p.mass, p.eps, p.L, R, ot.Table(24, 16, 20.0), 1, 0.6, 0.3, 0.9,
+                         leaf_size=4, group=64, stats=st)
+    n_cells, n_c, n_p = sc.steps_cyl_tree_info(t)
+    assert (n_cells, n_c, n_p) == (st["cells"], st["cell_interactions"], st["particle_interactions"])
+    a = a.double().cpu().numpy()
+    if case == "one":
+        assert np.all(a == 0.0) and np.all(ref == 0.0)
+    else:
+        scale = np.linalg.norm(ref, axis=0).max()
+        err = np.linalg.norm(a - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), 1e-3 * scale)
+        print(f"{case}: cells {n_cells}, max rel err {err.max():.2e}")
+        assert err.max() <= 2e-5
+    t.close()
+    tab.close()
