@@ -299,26 +299,29 @@ def tree_leg(args, dev):
     acc = torch.empty((3, N), dtype=torch.float32, device=dev)
     sc.steps_cyl_tree_forces(tree, pos, m, e, p.L, R, table, 1, 0.5, 0.0, 0.0, out_acc=acc)  # warm-up
     torch.cuda.synchronize()
+    quad_tree = sc.Octree(16, quadrupole=True)
     rows = []
-    for theta in args.tree_theta:
-        ms = []
-        for _ in range(3):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            sc.steps_cyl_tree_forces(tree, pos, m, e, p.L, R, table, 1, theta, rng.random() * p.L,
-                                     rng.random() * 2 * math.pi, out_acc=acc, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms.append(e0.elapsed_time(e1))
-        _, n_c, n_p = sc.steps_cyl_tree_info(tree)
-        a = acc[:, t].double()
-        err = (torch.linalg.norm(a - ref, dim=0) / torch.linalg.norm(ref, dim=0)).cpu().numpy()
-        rows.append({"theta": theta, "ms": round(float(np.median(ms)), 2),
-                     "interactions_per_particle": round((n_c + n_p) / N, 1),
-                     "mean_rel_err": float(f"{err.mean():.3e}"), "max_rel_err": float(f"{err.max():.3e}")})
-        print(f"[bench] tree N={N} theta={theta} {rows[-1]}", file=sys.stderr, flush=True)
+    for quad, tr in ((False, tree), (True, quad_tree)):
+        for theta in args.tree_theta:
+            ms = []
+            for _ in range(3):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                sc.steps_cyl_tree_forces(tr, pos, m, e, p.L, R, table, 1, theta, rng.random() * p.L,
+                                         rng.random() * 2 * math.pi, out_acc=acc, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            _, n_c, n_p = sc.steps_cyl_tree_info(tr)
+            a = acc[:, t].double()
+            err = (torch.linalg.norm(a - ref, dim=0) / torch.linalg.norm(ref, dim=0)).cpu().numpy()
+            rows.append({"theta": theta, "quadrupole": quad, "ms": round(float(np.median(ms)), 2),
+                         "interactions_per_particle": round((n_c + n_p) / N, 1),
+                         "mean_rel_err": float(f"{err.mean():.3e}"), "max_rel_err": float(f"{err.max():.3e}")})
+            print(f"[bench] tree N={N} {rows[-1]}", file=sys.stderr, flush=True)
     tree.close()
+    quad_tree.close()
     table.close()
     return {"N": N, "workload": f"stereographic cylinder load N={N} (seed 0), octree with leaf size 16 "
                                 "and 64-particle groups, complete 144x128 table (CIC); error vs the "

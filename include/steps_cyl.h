@@ -310,7 +310,8 @@ int steps_cyl_forces_table(const double *pos, const double *mass, const double *
  * the frame rotated by `angle` about the axis and shifted by `shift` along
  * it (z wrapped into [0, L)); R_dom must bound the particles' radius.  Cells
  * are split while they hold more than leaf_size particles (down to level
- * 21); each acts through its mass at its centre of mass.  Particles are
+ * 21); each acts through its mass at its centre of mass (and optionally
+ * its quadrupole).  Particles are
  * grouped for the walk into runs of at most 64 made of whole sibling cells
  * (children of a cell holding more than 64, packed in order); a group walks
  * the tree together and accepts a cell when (S0/2^level)^2 < theta^2 d^2 and
@@ -327,8 +328,12 @@ int steps_cyl_forces_table(const double *pos, const double *mass, const double *
  * ---------------------------------------------------------------------- */
 typedef struct steps_cyl_tree steps_cyl_tree;   /* opaque */
 
-/* 1 <= leaf_size <= 64.  No device work. */
-int steps_cyl_tree_create(int leaf_size, steps_cyl_tree **out);
+/* 1 <= leaf_size <= 64.  quadrupole 1: cells also carry their traceless
+ * quadrupole about the centre of mass, Q_ab = sum m (3 y_a y_b - |y|^2 d_ab),
+ * which adds Q s/r^5 - (5/2)(s.Q.s) s/r^7 for each of the three nearest
+ * images of an accepted cell (the table's band stays a monopole); 0:
+ * monopoles only.  No device work. */
+int steps_cyl_tree_create(int leaf_size, int quadrupole, steps_cyl_tree **out);
 
 /* Releases the tree and its buffers (NULL is ignored). */
 void steps_cyl_tree_destroy(steps_cyl_tree *tree);

@@ -19,7 +19,12 @@ leaves open is fixed here (each is a reading):
   more than ``leaf_size`` particles and is above level 21.  The cells form
   a list in depth-first order (children by octant) with, for each cell, the
   index of the first cell after its subtree ("skip").
-* Monopoles.  A cell acts through its mass at its centre of mass.
+* Multipoles.  A cell acts through its mass at its centre of mass and,
+  optionally, its traceless quadrupole about the centre of mass,
+  Q_ab = sum m (3 y_a y_b - |y|^2 delta_ab), y = x - x_com, which adds
+  Q s / r^5 - (5/2) (s.Q.s) s / r^7 to the acceleration at separation s
+  (target minus centre of mass) for each of the three nearest images; the
+  table's band stays a monopole.
 * Groups.  Targets walk the tree in groups of at most ``group`` particles
   made of whole sibling cells: for every cell holding more than ``group``
   particles, its children (in order) that hold at most ``group`` are packed
@@ -86,7 +91,7 @@ class Tree:
     """Cells in depth-first order: level, [start, end) in key order, mass,
     centre of mass (3), largest softening, leaf flag, skip index."""
 
-    def __init__(self, pos, mass, eps, L, R_dom, shift=0.0, angle=0.0, leaf_size=16):
+    def __init__(self, pos, mass, eps, L, R_dom, shift=0.0, angle=0.0, leaf_size=16, quadrupole=False):
         self.L, self.leaf_size = float(L), int(leaf_size)
         self.lo, self.side = root_cube(L, R_dom)
         self.pos_t = transform(np.asarray(pos, dtype=np.float64), L, shift, angle)
@@ -107,6 +112,16 @@ class Tree:
         self.hmax = np.array([c[5] for c in self.cells])
         self.leaf = np.array([c[6] for c in self.cells])
         self.skip = np.array([c[7] for c in self.cells])
+        self.quad = np.zeros((6, len(self.cells)))   # xx, yy, zz, xy, xz, yz
+        if quadrupole:
+            for k in range(len(self.cells)):
+                sl = slice(self.start[k], self.end[k])
+                y = self.sp[:, sl] - self.com[:, k:k + 1]
+                m = self.sm[sl]
+                y2 = (y * y).sum(axis=0)
+                self.quad[:, k] = [np.sum(m * (3 * y[0] * y[0] - y2)), np.sum(m * (3 * y[1] * y[1] - y2)),
+                                   np.sum(m * (3 * y[2] * y[2] - y2)), np.sum(m * 3 * y[0] * y[1]),
+                                   np.sum(m * 3 * y[0] * y[2]), np.sum(m * 3 * y[1] * y[2])]
 
     def _build(self, level, start, end):
         m = self.sm[start:end]
@@ -182,6 +197,22 @@ def box_distance2(c, lo, hi, L):
     return dx * dx + dy * dy + dz * dz
 
 
+def _quadrupole(tree, tg, c, q, acc):
+    """Quadrupole term of one cell (centre of mass c, moments q) on the
+    targets tg, images n = -1, 0, 1 about the minimum image."""
+    L = tree.L
+    tp = tree.sp[:, tg]
+    t = tp[2] - c[2]
+    d = t - L * np.floor(t / L + 0.5)
+    Q = np.array([[q[0], q[3], q[4]], [q[3], q[1], q[5]], [q[4], q[5], q[2]]])
+    for n in (-1, 0, 1):
+        s = np.stack([tp[0] - c[0], tp[1] - c[1], d - n * L])
+        r2 = (s * s).sum(axis=0)
+        Qs = Q @ s
+        sQs = (s * Qs).sum(axis=0)
+        acc[:, tg] += Qs / r2 ** 2.5 - 2.5 * sQs * s / r2 ** 3.5
+
+
 def _interact(tree, tg, src_pos, src_m, src_h, src_id, tab, order, acc):
     """Targets tg (sorted indices) against sources: near images + band."""
     L = tree.L
@@ -200,11 +231,11 @@ def _interact(tree, tg, src_pos, src_m, src_h, src_id, tab, order, acc):
 
 
 def tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, shift=0.0, angle=0.0,
-                leaf_size=16, group=64, stats=None, targets=None):
+                leaf_size=16, group=64, stats=None, targets=None, quadrupole=False):
     """Accelerations (3, N) of every particle by the octree (G = 1), in the
     original frame and order; with ``targets`` (original indices) only the
     groups holding them are walked and (3, len(targets)) is returned."""
-    T = Tree(pos, mass, eps, L, R_dom, shift, angle, leaf_size)
+    T = Tree(pos, mass, eps, L, R_dom, shift, angle, leaf_size, quadrupole)
     N = T.sm.size
     acc = np.zeros((3, N))     # in key order, transformed frame
     n_cell = n_part = 0
@@ -228,6 +259,8 @@ def tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, shift=0.0, angle=0.
             if T.size(k) * T.size(k) < theta2 * d2 and d2 > hs * hs:
                 _interact(T, tg, T.com[:, k:k + 1], T.mass[k:k + 1], T.hmax[k:k + 1],
                           np.array([-1]), tab, order, acc)
+                if quadrupole:
+                    _quadrupole(T, tg, T.com[:, k], T.quad[:, k], acc)
                 n_cell += tg.size
                 k = T.skip[k]
             elif T.leaf[k]:
@@ -261,13 +294,14 @@ def radial_bins(pos, acc_err, R_dom, n_bins):
 
 
 def calibrate(pos, mass, eps, L, R_dom, tab, order, theta, shifts, angles, n_bins,
-              leaf_size=16, group=64):
+              leaf_size=16, group=64, quadrupole=False):
     """Mean radial error (tree - direct) per radial bin over the realisations."""
     direct = ot.forces_table(pos, mass, eps, L, tab, order)
     sums = np.zeros(n_bins)
     counts = np.zeros(n_bins)
     for s, a in zip(shifts, angles):
-        t = tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, s, a, leaf_size, group)
+        t = tree_forces(pos, mass, eps, L, R_dom, tab, order, theta, s, a, leaf_size, group,
+                        quadrupole=quadrupole)
         ds, dc = radial_bins(pos, t - direct, R_dom, n_bins)
         sums += ds
         counts += dc

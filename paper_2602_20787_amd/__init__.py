@@ -112,7 +112,7 @@ _SIGNATURES = {
     "steps_cyl_table_create_ewald": [_I32, _I32, _F64, _F64, _I32, _I32, _I32, _VP, _PP],
     "steps_cyl_table_values_f64": [_VP, _VP],
     "steps_cyl_table_info": [_VP, _VP, _VP, _VP, _VP],
-    "steps_cyl_tree_create": [_I32, _PP],
+    "steps_cyl_tree_create": [_I32, _I32, _PP],
     "steps_cyl_tree_forces": [_VP, _VP, _VP, _VP, _I64, _F64, _F64, _VP, _I32, _F64, _F64, _F64, _I32,
                               _VP, _VP],
     "steps_cyl_tree_calibrate": [_VP, _VP, _VP, _VP, _I64, _F64, _F64, _VP, _I32, _F64, _VP, _VP,
@@ -605,9 +605,9 @@ def steps_cyl_forces_table(pos, mass, eps, L, table, order=2, targets=None, out_
 
 
 # ---------------------------------------------------------------- octree
-def steps_cyl_tree_create(leaf_size=16):
+def steps_cyl_tree_create(leaf_size=16, quadrupole=False):
     h = ctypes.c_void_p()
-    _check(lib().steps_cyl_tree_create(int(leaf_size), ctypes.byref(h)))
+    _check(lib().steps_cyl_tree_create(int(leaf_size), 1 if quadrupole else 0, ctypes.byref(h)))
     return h.value
 
 
@@ -687,9 +687,9 @@ def steps_cyl_tree_cells(tree, N):
 class Octree:
     """Owning wrapper of a tree handle."""
 
-    def __init__(self, leaf_size=16):
-        self.leaf_size = leaf_size
-        self.handle = steps_cyl_tree_create(leaf_size)
+    def __init__(self, leaf_size=16, quadrupole=False):
+        self.leaf_size, self.quadrupole = leaf_size, bool(quadrupole)
+        self.handle = steps_cyl_tree_create(leaf_size, quadrupole)
 
     def close(self):
         if self.handle:

@@ -49,10 +49,12 @@ constexpr int kBlock = 256;
 constexpr int kMaxBins = 256;
 constexpr int kGroup = 64;
 
-// one cell in depth-first order (64 B)
+// one cell in depth-first order (88 B): monopole, and the traceless
+// quadrupole about the centre of mass (xx, yy, zz, xy, xz, yz) when enabled
 struct CellRec {
     double cx, cy, cz, mass, hmax, size;
     int start, count, skip, leaf;
+    float q[6];
 };
 
 }  // namespace
@@ -60,6 +62,7 @@ struct CellRec {
 
 struct steps_cyl_tree {
     int leaf_size = 16;
+    int quadrupole = 0;
     int64_t cap_n = 0, cap_cells = 0;
     size_t cub_bytes = 0;
     void *cub_tmp = nullptr;
@@ -72,6 +75,7 @@ struct steps_cyl_tree {
     // cells, in build order (level by level)
     int *c_start = nullptr, *c_count = nullptr, *c_level = nullptr, *c_leaf = nullptr;
     double *c_m = nullptr, *c_mx = nullptr, *c_my = nullptr, *c_mz = nullptr, *c_h = nullptr;
+    double *c_q = nullptr;  // [6][cap_cells] quadrupoles (when enabled)
     uint64_t *c_key_in = nullptr, *c_key_out = nullptr;
     int *c_id_in = nullptr, *c_id_out = nullptr;
     steps::CellRec *cells = nullptr;  // depth-first
@@ -153,6 +157,11 @@ hipError_t ensure_cells(steps_cyl_tree *t, int64_t n, hipStream_t stream) {
     regrow(t->c_my);
     regrow(t->c_mz);
     regrow(t->c_h);
+    if (e == hipSuccess) {  // filled after the last level: nothing to keep
+        (void)hipFree(t->c_q);
+        t->c_q = nullptr;
+        e = hipMalloc(&t->c_q, (size_t)6 * c * sizeof(double));
+    }
     regrow(t->c_key_in);
     regrow(t->c_key_out);
     regrow(t->c_id_in);
@@ -321,6 +330,47 @@ __global__ void moments_kernel(int off, int n, int child_off, int n_child, const
     c_h[c] = h;
 }
 
+// traceless quadrupole about the centre of mass, one level's cells: leaves
+// from their particles, cells from their children (parallel-axis shift)
+__global__ void quadrupole_kernel(int off, int n, int child_off, int n_child, int cap, const int *c_start,
+                                  const int *c_count, const int *c_leaf, const double *c_m, const double *c_mx,
+                                  const double *c_my, const double *c_mz, double *c_q, const double *sx,
+                                  const double *sy, const double *sz, const double *sm) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int c = off + k;
+    const int s = c_start[c], e = s + c_count[c];
+    double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double m = c_m[c];
+    if (m > 0.0) {
+        const double gx = c_mx[c] / m, gy = c_my[c] / m, gz = c_mz[c] / m;
+        auto add = [&](double w, double x, double y, double z) {
+            const double r2 = x * x + y * y + z * z;
+            q[0] += w * (3.0 * x * x - r2);
+            q[1] += w * (3.0 * y * y - r2);
+            q[2] += w * (3.0 * z * z - r2);
+            q[3] += w * 3.0 * x * y;
+            q[4] += w * 3.0 * x * z;
+            q[5] += w * 3.0 * y * z;
+        };
+        if (c_leaf[c]) {
+            for (int j = s; j < e; ++j) add(sm[j], sx[j] - gx, sy[j] - gy, sz[j] - gz);
+        } else {
+            int lo = 0, hi = n_child - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) / 2;
+                if (c_start[child_off + mid] < s) lo = mid + 1; else hi = mid;
+            }
+            for (int ch = child_off + lo; ch < child_off + n_child && c_start[ch] < e; ++ch) {
+                const double mc = c_m[ch];
+                for (int a = 0; a < 6; ++a) q[a] += c_q[(size_t)a * cap + ch];
+                if (mc > 0.0) add(mc, c_mx[ch] / mc - gx, c_my[ch] / mc - gy, c_mz[ch] / mc - gz);
+            }
+        }
+    }
+    for (int a = 0; a < 6; ++a) c_q[(size_t)a * cap + c] = q[a];
+}
+
 __global__ void dfs_keys_kernel(int n, const int *c_start, const int *c_level, uint64_t *key, int *id) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -331,7 +381,8 @@ __global__ void dfs_keys_kernel(int n, const int *c_start, const int *c_level, u
 __global__ void dfs_cells_kernel(int n, int N, const uint64_t *key, const int *id, const int *c_start,
                                  const int *c_count, const int *c_level, const int *c_leaf, const double *c_m,
                                  const double *c_mx, const double *c_my, const double *c_mz, const double *c_h,
-                                 const uint64_t *pkey, Frame f, double side, CellRec *cells, int *cell_level) {
+                                 const double *c_q, int cap, int quad, const uint64_t *pkey, Frame f, double side,
+                                 CellRec *cells, int *cell_level) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int c = id[p];
@@ -366,6 +417,7 @@ __global__ void dfs_cells_kernel(int n, int N, const uint64_t *key, const int *i
     r.count = c_count[c];
     r.skip = skip;
     r.leaf = c_leaf[c];
+    for (int a = 0; a < 6; ++a) r.q[a] = quad ? (float)c_q[(size_t)a * cap + c] : 0.f;
     cells[p] = r;
     cell_level[p] = c_level[c];
 }
@@ -466,7 +518,33 @@ __device__ bool accept_cell(const CellRec &r, const double lo[3], const double h
     return r.size * r.size < theta2 * d2 && d2 > hs * hs;
 }
 
-template <int ORDER>
+// quadrupole term of an accepted cell for the images n = -1, 0, 1 about the
+// minimum image, subtracted from the partial sums (which carry the opposite
+// sign of the acceleration): a += Q s / r^5 - (5/2) (s.Q.s) s / r^7
+__device__ __forceinline__ void quadrupole_term(const CellRec &r, double xi, double yi, double zi,
+                                                const PeriodConsts &pc, float &px, float &py, float &pz) {
+    const float sx = (float)(xi - r.cx), sy = (float)(yi - r.cy);
+    const float d = (float)min_image(zi - r.cz, pc.L, pc.invL);
+    const float rho2 = __builtin_fmaf(sx, sx, sy * sy);
+#pragma unroll
+    for (int n = -1; n <= 1; ++n) {
+        const float sz = d - (float)n * pc.c.Lf;
+        const float r2 = __builtin_fmaf(sz, sz, rho2);
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float ri2 = ri * ri;
+        const float ri5 = ri2 * ri2 * ri;
+        const float qx = __builtin_fmaf(r.q[0], sx, __builtin_fmaf(r.q[3], sy, r.q[4] * sz));
+        const float qy = __builtin_fmaf(r.q[3], sx, __builtin_fmaf(r.q[1], sy, r.q[5] * sz));
+        const float qz = __builtin_fmaf(r.q[4], sx, __builtin_fmaf(r.q[5], sy, r.q[2] * sz));
+        const float sqs = __builtin_fmaf(sx, qx, __builtin_fmaf(sy, qy, sz * qz));
+        const float c = -2.5f * sqs * ri2;
+        px = __builtin_fmaf(-ri5, __builtin_fmaf(c, sx, qx), px);
+        py = __builtin_fmaf(-ri5, __builtin_fmaf(c, sy, qy), py);
+        pz = __builtin_fmaf(-ri5, __builtin_fmaf(c, sz, qz), pz);
+    }
+}
+
+template <int ORDER, bool QUAD>
 __global__ __launch_bounds__(kBlock) void tree_walk_kernel(WalkArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
@@ -496,6 +574,7 @@ __global__ __launch_bounds__(kBlock) void tree_walk_kernel(WalkArgs a) {
             src.m = (float)r.mass;
             src.h = (float)r.hmax;
             table_pair<ORDER, false>(a.tv, a.pc, xi, yi, zi, hi, src, false, active, px, py, pz, pp);
+            if (QUAD) quadrupole_term(r, xi, yi, zi, a.pc, px, py, pz);
             ++n_cell;
             if (++pending == 16) {
                 kahan_add(sx, cx, px);
@@ -688,6 +767,12 @@ int build(steps_cyl_tree *t, const double *pos, const double *mass, const double
                            t->c_start, t->c_count, t->c_leaf, t->c_m, t->c_mx, t->c_my, t->c_mz, t->c_h, t->sx, t->sy,
                            t->sz, t->sm, t->sh);
         TRY(hipGetLastError());
+        if (t->quadrupole) {
+            hipLaunchKernelGGL(quadrupole_kernel, dim3(blocks(cnt[l])), dim3(kBlock), 0, stream, off[l], cnt[l], co,
+                               cn, (int)t->cap_cells, t->c_start, t->c_count, t->c_leaf, t->c_m, t->c_mx, t->c_my,
+                               t->c_mz, t->c_q, t->sx, t->sy, t->sz, t->sm);
+            TRY(hipGetLastError());
+        }
     }
     // depth-first order and skip links
     hipLaunchKernelGGL(dfs_keys_kernel, dim3(blocks(total)), dim3(kBlock), 0, stream, total, t->c_start, t->c_level,
@@ -698,7 +783,8 @@ int build(steps_cyl_tree *t, const double *pos, const double *mass, const double
                                            total, 0, 37, stream));
     hipLaunchKernelGGL(dfs_cells_kernel, dim3(blocks(total)), dim3(kBlock), 0, stream, total, n, t->c_key_out,
                        t->c_id_out, t->c_start, t->c_count, t->c_level, t->c_leaf, t->c_m, t->c_mx, t->c_my, t->c_mz,
-                       t->c_h, t->key_out, f, side, t->cells, t->cell_level);
+                       t->c_h, t->c_q, (int)t->cap_cells, t->quadrupole, t->key_out, f, side, t->cells,
+                       t->cell_level);
     TRY(hipGetLastError());
     // target groups
     hipLaunchKernelGGL(group_count_kernel, dim3(blocks(total)), dim3(kBlock), 0, stream, t->cells, total, t->g_cnt);
@@ -746,10 +832,18 @@ int walk(steps_cyl_tree *t, const steps_cyl_table *table, int order, double L, d
     a.N = (int)t->n;
     a.n_cells = (int)t->n_cells;
     const int64_t threads = t->n_groups * 64;
-    if (order == 1)
-        hipLaunchKernelGGL(tree_walk_kernel<1>, dim3(blocks(threads)), dim3(kBlock), 0, stream, a);
-    else
-        hipLaunchKernelGGL(tree_walk_kernel<2>, dim3(blocks(threads)), dim3(kBlock), 0, stream, a);
+    const dim3 grid(blocks(threads)), block(kBlock);
+    if (t->quadrupole) {
+        if (order == 1)
+            hipLaunchKernelGGL((tree_walk_kernel<1, true>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((tree_walk_kernel<2, true>), grid, block, 0, stream, a);
+    } else {
+        if (order == 1)
+            hipLaunchKernelGGL((tree_walk_kernel<1, false>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((tree_walk_kernel<2, false>), grid, block, 0, stream, a);
+    }
     return hip_status(hipGetLastError(), "tree walk");
 }
 
@@ -768,13 +862,15 @@ int check_common(const double *pos, const double *mass, const double *eps, int64
 
 using namespace steps;
 
-STEPS_API int steps_cyl_tree_create(int leaf_size, steps_cyl_tree **out) {
+STEPS_API int steps_cyl_tree_create(int leaf_size, int quadrupole, steps_cyl_tree **out) {
     if (!out) return fail(STEPS_EINVAL, "out must be non-null");
     if (leaf_size < 1 || leaf_size > 64) return fail(STEPS_EINVAL, "leaf_size=%d outside [1, 64]", leaf_size);
+    if (quadrupole != 0 && quadrupole != 1) return fail(STEPS_EINVAL, "quadrupole must be 0 or 1");
     clear_error();
     steps_cyl_tree *t = new (std::nothrow) steps_cyl_tree();
     if (!t) return fail(STEPS_ENOMEM, "out of host memory");
     t->leaf_size = leaf_size;
+    t->quadrupole = quadrupole;
     *out = t;
     return STEPS_OK;
 }
@@ -783,7 +879,7 @@ STEPS_API void steps_cyl_tree_destroy(steps_cyl_tree *t) {
     if (!t) return;
     void *ptrs[] = {t->cub_tmp, t->tx, t->ty, t->tz, t->key_in, t->key_out, t->idx_in, t->idx_out, t->sx, t->sy,
                     t->sz, t->sm, t->sh, t->act, t->fs, t->fe, t->ss, t->se, t->c_start, t->c_count, t->c_level,
-                    t->c_leaf, t->c_m, t->c_mx, t->c_my, t->c_mz, t->c_h, t->c_key_in, t->c_key_out, t->c_id_in,
+                    t->c_leaf, t->c_m, t->c_mx, t->c_my, t->c_mz, t->c_h, t->c_q, t->c_key_in, t->c_key_out, t->c_id_in,
                     t->c_id_out, t->cells, t->cell_level, t->wave_cells, t->wave_parts, t->corr, t->bin_sum,
                     t->g_cnt, t->g_off, t->g_start, t->g_count,
                     t->bin_cnt, t->acc_dir, t->acc_tree};

@@ -224,10 +224,11 @@ def test_tree_calls_reject_bad_arguments():
     L = sc.lib()
     P = ctypes.c_void_p(64)
     h = ctypes.c_void_p()
-    assert L.steps_cyl_tree_create(0, ctypes.byref(h)) == sc.STEPS_EINVAL
-    assert L.steps_cyl_tree_create(65, ctypes.byref(h)) == sc.STEPS_EINVAL
-    assert L.steps_cyl_tree_create(16, None) == sc.STEPS_EINVAL
-    assert L.steps_cyl_tree_create(16, ctypes.byref(h)) == sc.STEPS_OK   # host object only
+    assert L.steps_cyl_tree_create(0, 0, ctypes.byref(h)) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_create(65, 0, ctypes.byref(h)) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_create(16, 2, ctypes.byref(h)) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_create(16, 0, None) == sc.STEPS_EINVAL
+    assert L.steps_cyl_tree_create(16, 1, ctypes.byref(h)) == sc.STEPS_OK   # host object only
     t = h.value
     f = L.steps_cyl_tree_forces
     assert f(None, P, P, P, 10, 1.0, 3.0, P, 1, 0.5, 0.0, 0.0, 0, P, None) == sc.STEPS_EINVAL

@@ -84,19 +84,20 @@ def test_zero_opening_angle_is_the_direct_kernel(sc):
     tab.close()
 
 
-@pytest.mark.parametrize("theta,order", [(0.3, 1), (0.6, 1), (1.0, 1), (0.6, 2)])
-def test_tree_forces_match_oracle(sc, theta, order):
+@pytest.mark.parametrize("theta,order,quad", [(0.3, 1, False), (0.6, 1, False), (1.0, 1, False),
+                                              (0.6, 2, False), (0.6, 1, True), (1.0, 2, True)])
+def test_tree_forces_match_oracle(sc, theta, order, quad):
     p = synth.clustered_load(2000, n_clumps=4, clump_frac=0.05, seed=33)
-    t = sc.Octree(16)
+    t = sc.Octree(16, quadrupole=quad)
     tab = sc.CorrectionTable(24, 16, 6.5, 1024)
     a = sc.steps_cyl_tree_forces(t, *to_dev(p), p.L, R, tab, order, theta, 0.6, 2.5)
     torch.cuda.synchronize()
     st = {}
     ref = oc.tree_forces(p.pos, p.mass, p.eps, p.L, R, ot.Table(24, 16, 6.5), order, theta, 0.6, 2.5,
-                         leaf_size=16, group=64, stats=st)
+                         leaf_size=16, group=64, stats=st, quadrupole=quad)
     n_cells, n_c, n_p = sc.steps_cyl_tree_info(t)
     err = rel(a.double().cpu().numpy(), ref)
-    print(f"theta={theta} order={order}: cells {n_cells}, cell/particle interactions {n_c}/{n_p}, "
+    print(f"theta={theta} order={order} quad={quad}: cells {n_cells}, cell/particle interactions {n_c}/{n_p}, "
           f"max rel err {err.max():.2e}")
     assert (n_cells, n_c, n_p) == (st["cells"], st["cell_interactions"], st["particle_interactions"])
     assert err.max() <= 2e-5
@@ -264,4 +265,24 @@ def test_edge_cases_match_oracle(sc, case):
         print(f"{case}: cells {n_cells}, max rel err {err.max():.2e}")
         assert err.max() <= 2e-5
     t.close()
+    tab.close()
+
+
+def test_quadrupoles_cut_the_error_at_equal_cost(sc):
+    # same acceptance decisions (same interaction counts), smaller error
+    p = synth.cylinder_load(1 << 15, seed=39)
+    pos, m, e = to_dev(p)
+    tab = sc.CorrectionTable(128, 144, 6.4, 1024)
+    d, _ = sc.steps_cyl_forces_table(pos, m, e, p.L, tab, order=1, potential=False)
+    d = d.double().cpu().numpy()
+    for theta in (0.3, 0.5):
+        out = {}
+        for quad in (False, True):
+            t = sc.Octree(16, quadrupole=quad)
+            a = sc.steps_cyl_tree_forces(t, pos, m, e, p.L, R, tab, 1, theta, 0.3, 0.7)
+            out[quad] = (rel(a.double().cpu().numpy(), d).mean(), sc.steps_cyl_tree_info(t))
+            t.close()
+        print(f"theta={theta}: mean error monopole {out[False][0]:.2e}, quadrupole {out[True][0]:.2e}")
+        assert out[False][1] == out[True][1]
+        assert out[True][0] < 0.5 * out[False][0]
     tab.close()

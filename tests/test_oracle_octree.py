@@ -168,3 +168,36 @@ def test_target_subset_walks_the_same_groups(load, tab):
     sub = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.5, 0.25, 1.7,
                          leaf_size=8, group=16, targets=tg)
     np.testing.assert_array_equal(sub, full[:, tg])
+
+
+def test_quadrupole_moments_converge_at_third_order():
+    # a compact cluster seen from afar: the monopole error falls as the
+    # cluster size squared, monopole + quadrupole as its cube
+    L = 1000.0
+    rng = np.random.default_rng(71)
+    Y = rng.normal(size=(3, 20))
+    m = rng.random(20)
+    x = np.array([0.6, -0.3, 0.5])
+    errs = []
+    for scale in (0.04, 0.02, 0.01):
+        pos = Y * scale + np.array([[0.0], [0.0], [L / 2]])
+        T = oc.Tree(pos, m, np.full(20, 1e-6), L, 2.0, quadrupole=True)
+        com, q = T.com[:, 0], T.quad[:, 0]
+        s = x + np.array([0.0, 0.0, L / 2]) - pos.T
+        exact = -(m[:, None] * s / (np.linalg.norm(s, axis=1) ** 3)[:, None]).sum(axis=0)
+        sc_ = x + np.array([0.0, 0.0, L / 2]) - com
+        r = np.linalg.norm(sc_)
+        mono = -m.sum() * sc_ / r ** 3
+        Q = np.array([[q[0], q[3], q[4]], [q[3], q[1], q[5]], [q[4], q[5], q[2]]])
+        quad = mono + Q @ sc_ / r ** 5 - 2.5 * (sc_ @ Q @ sc_) * sc_ / r ** 7
+        errs.append((np.linalg.norm(mono - exact), np.linalg.norm(quad - exact)))
+    for (m0, q0), (m1, q1) in zip(errs[:-1], errs[1:]):
+        assert 3.5 < m0 / m1 < 4.5
+        assert 7.0 < q0 / q1 < 9.0
+
+
+def test_quadrupole_walk_is_more_accurate(load, tab, direct):
+    a = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.4, 0.2, 0.4, leaf_size=8, group=16)
+    b = oc.tree_forces(load.pos, load.mass, load.eps, load.L, R, tab, 1, 0.4, 0.2, 0.4, leaf_size=8, group=16,
+                       quadrupole=True)
+    assert rel(b, direct).mean() < 0.5 * rel(a, direct).mean()
