@@ -330,9 +330,9 @@ typedef struct steps_cyl_tree steps_cyl_tree;   /* opaque */
 
 /* 1 <= leaf_size <= 64.  quadrupole 1: cells also carry their traceless
  * quadrupole about the centre of mass, Q_ab = sum m (3 y_a y_b - |y|^2 d_ab),
- * which adds Q s/r^5 - (5/2)(s.Q.s) s/r^7 for each of the three nearest
- * images of an accepted cell (the table's band stays a monopole); 0:
- * monopoles only.  No device work. */
+ * which adds Q s/r^5 - (5/2)(s.Q.s) s/r^7 for each image |n| <= 4 of an
+ * accepted cell (the table's band beyond stays a monopole); 0: monopoles
+ * only.  No device work. */
 int steps_cyl_tree_create(int leaf_size, int quadrupole, steps_cyl_tree **out);
 
 /* Releases the tree and its buffers (NULL is ignored). */

@@ -23,8 +23,9 @@ leaves open is fixed here (each is a reading):
   optionally, its traceless quadrupole about the centre of mass,
   Q_ab = sum m (3 y_a y_b - |y|^2 delta_ab), y = x - x_com, which adds
   Q s / r^5 - (5/2) (s.Q.s) s / r^7 to the acceleration at separation s
-  (target minus centre of mass) for each of the three nearest images; the
-  table's band stays a monopole.
+  (target minus centre of mass) for each image |n| <= 4 about the minimum
+  image (the table's band beyond carries only the monopole: the quadrupole
+  term falls as 1/n^4).
 * Groups.  Targets walk the tree in groups of at most ``group`` particles
   made of whole sibling cells: for every cell holding more than ``group``
   particles, its children (in order) that hold at most ``group`` are packed
@@ -197,15 +198,18 @@ def box_distance2(c, lo, hi, L):
     return dx * dx + dy * dy + dz * dz
 
 
+QUAD_IMAGES = 4
+
+
 def _quadrupole(tree, tg, c, q, acc):
     """Quadrupole term of one cell (centre of mass c, moments q) on the
-    targets tg, images n = -1, 0, 1 about the minimum image."""
+    targets tg, images |n| <= QUAD_IMAGES about the minimum image."""
     L = tree.L
     tp = tree.sp[:, tg]
     t = tp[2] - c[2]
     d = t - L * np.floor(t / L + 0.5)
     Q = np.array([[q[0], q[3], q[4]], [q[3], q[1], q[5]], [q[4], q[5], q[2]]])
-    for n in (-1, 0, 1):
+    for n in range(-QUAD_IMAGES, QUAD_IMAGES + 1):
         s = np.stack([tp[0] - c[0], tp[1] - c[1], d - n * L])
         r2 = (s * s).sum(axis=0)
         Qs = Q @ s

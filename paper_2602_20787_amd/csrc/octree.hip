@@ -518,24 +518,31 @@ __device__ bool accept_cell(const CellRec &r, const double lo[3], const double h
     return r.size * r.size < theta2 * d2 && d2 > hs * hs;
 }
 
-// quadrupole term of an accepted cell for the images n = -1, 0, 1 about the
-// minimum image, subtracted from the partial sums (which carry the opposite
-// sign of the acceleration): a += Q s / r^5 - (5/2) (s.Q.s) s / r^7
+// quadrupole term of an accepted cell for the images |n| <= 4 about the
+// minimum image (beyond, the term falls as 1/n^4), subtracted from the
+// partial sums (which carry the opposite sign of the acceleration):
+// a += Q s / r^5 - (5/2) (s.Q.s) s / r^7.  Q s_n = Q s_0 - n L Q e_z.
+constexpr int kQuadImages = 4;
+
 __device__ __forceinline__ void quadrupole_term(const CellRec &r, double xi, double yi, double zi,
                                                 const PeriodConsts &pc, float &px, float &py, float &pz) {
     const float sx = (float)(xi - r.cx), sy = (float)(yi - r.cy);
     const float d = (float)min_image(zi - r.cz, pc.L, pc.invL);
     const float rho2 = __builtin_fmaf(sx, sx, sy * sy);
+    const float bx = __builtin_fmaf(r.q[0], sx, __builtin_fmaf(r.q[3], sy, r.q[4] * d));
+    const float by = __builtin_fmaf(r.q[3], sx, __builtin_fmaf(r.q[1], sy, r.q[5] * d));
+    const float bz = __builtin_fmaf(r.q[4], sx, __builtin_fmaf(r.q[5], sy, r.q[2] * d));
 #pragma unroll
-    for (int n = -1; n <= 1; ++n) {
-        const float sz = d - (float)n * pc.c.Lf;
+    for (int n = -kQuadImages; n <= kQuadImages; ++n) {
+        const float nL = (float)n * pc.c.Lf;
+        const float sz = d - nL;
+        const float qx = __builtin_fmaf(-nL, r.q[4], bx);
+        const float qy = __builtin_fmaf(-nL, r.q[5], by);
+        const float qz = __builtin_fmaf(-nL, r.q[2], bz);
         const float r2 = __builtin_fmaf(sz, sz, rho2);
         const float ri = __builtin_amdgcn_rsqf(r2);
         const float ri2 = ri * ri;
         const float ri5 = ri2 * ri2 * ri;
-        const float qx = __builtin_fmaf(r.q[0], sx, __builtin_fmaf(r.q[3], sy, r.q[4] * sz));
-        const float qy = __builtin_fmaf(r.q[3], sx, __builtin_fmaf(r.q[1], sy, r.q[5] * sz));
-        const float qz = __builtin_fmaf(r.q[4], sx, __builtin_fmaf(r.q[5], sy, r.q[2] * sz));
         const float sqs = __builtin_fmaf(sx, qx, __builtin_fmaf(sy, qy, sz * qz));
         const float c = -2.5f * sqs * ri2;
         px = __builtin_fmaf(-ri5, __builtin_fmaf(c, sx, qx), px);
