@@ -356,7 +356,10 @@ int steps_cyl_tree_forces(steps_cyl_tree *tree, const double *pos, const double 
  * (host arrays shifts[n_real], angles[n_real], the caller's random draws);
  * stored in the tree and copied to out_corr (host [n_bins], may be NULL).
  * Applied by linear interpolation between bin centres, constant beyond the
- * first and the last.  1 <= n_real <= 1024, 1 <= n_bins <= 256.  Synchronous. */
+ * first and the last.  1 <= n_real <= 1024, 1 <= n_bins <= 256.  Costs one
+ * direct tabulated evaluation (O(N^2)) plus n_real tree evaluations; its
+ * scratch (two [3][N] FP32 force arrays, the bins) is kept by the tree.
+ * Synchronous. */
 int steps_cyl_tree_calibrate(steps_cyl_tree *tree, const double *pos, const double *mass,
                              const double *eps, int64_t N, double L, double R_dom,
                              const steps_cyl_table *table, int order, double theta,
