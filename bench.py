@@ -328,6 +328,28 @@ def tree_leg(args, dev):
                                 "direct tabulated force on 4096 targets", "runs": rows}
 
 
+def table_build_leg(dev):
+    """Build times of the 144 x 128 correction tables: the direct sum over
+    10^7 images per side (the reference table of Fig. 2, which the paper
+    quotes at about 10^4 s) and the complete table from the Ewald split."""
+    import torch
+
+    import paper_2602_20787_amd as sc
+
+    out = {}
+    for name, make in (("direct_1e7_images", lambda: sc.CorrectionTable(128, 144, 6.4, 10 ** 7)),
+                       ("ewald_complete", lambda: sc.CorrectionTable.ewald(128, 144, 6.4, 2.0, 5, 12))):
+        make().close()  # first use: code objects and allocations
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t = make()          # synchronous build
+        out[name + "_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+        t.close()
+    out["image_terms_direct"] = 147 * 131 * 2 * (10 ** 7 - 1)
+    print(f"[bench] table builds {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def copy_leg(dev):
     """A 256 MiB device-to-device copy, the yardstick for HBM byte counters."""
     import torch
@@ -363,6 +385,8 @@ def main():
     ap.add_argument("--tree-n", type=int, default=1 << 20,
                     help="particles of the octree leg (0 skips it)")
     ap.add_argument("--tree-theta", type=float, nargs="+", default=[0.3, 0.5, 0.7])
+    ap.add_argument("--no-table-build", action="store_true",
+                    help="skip timing the 144 x 128 table builds")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -383,6 +407,8 @@ def main():
         out["learned"] = learned_leg(args, dev)
     if args.tree_n:
         out["octree"] = tree_leg(args, dev)
+    if not args.no_table_build:
+        out["table_build"] = table_build_leg(dev)
     if args.copy_calib:
         out["copy_calib"] = copy_leg(dev)
     print(json.dumps(out), flush=True)

@@ -551,7 +551,7 @@ __device__ __forceinline__ void quadrupole_term(const CellRec &r, double xi, dou
     }
 }
 
-template <int ORDER, bool QUAD>
+template <int ORDER, bool QUAD, bool COMPLETE>
 __global__ __launch_bounds__(kBlock) void tree_walk_kernel(WalkArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void tree_walk_kernel(WalkArgs a) {
             src.z = r.cz;
             src.m = (float)r.mass;
             src.h = (float)r.hmax;
-            table_pair<ORDER, false>(a.tv, a.pc, xi, yi, zi, hi, src, false, active, px, py, pz, pp);
+            table_pair<ORDER, false, COMPLETE>(a.tv, a.pc, xi, yi, zi, hi, src, false, active, px, py, pz, pp);
             if (QUAD) quadrupole_term(r, xi, yi, zi, a.pc, px, py, pz);
             ++n_cell;
             if (++pending == 16) {
@@ -600,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void tree_walk_kernel(WalkArgs a) {
                 src.z = a.sz[j];
                 src.m = (float)a.sm[j];
                 src.h = (float)a.sh[j];
-                table_pair<ORDER, false>(a.tv, a.pc, xi, yi, zi, hi, src, j == i, active, px, py, pz, pp);
+                table_pair<ORDER, false, COMPLETE>(a.tv, a.pc, xi, yi, zi, hi, src, j == i, active, px, py, pz, pp);
             }
             n_part += r.count;
             kahan_add(sx, cx, px);
@@ -840,16 +840,16 @@ int walk(steps_cyl_tree *t, const steps_cyl_table *table, int order, double L, d
     a.n_cells = (int)t->n_cells;
     const int64_t threads = t->n_groups * 64;
     const dim3 grid(blocks(threads)), block(kBlock);
-    if (t->quadrupole) {
-        if (order == 1)
-            hipLaunchKernelGGL((tree_walk_kernel<1, true>), grid, block, 0, stream, a);
-        else
-            hipLaunchKernelGGL((tree_walk_kernel<2, true>), grid, block, 0, stream, a);
-    } else {
-        if (order == 1)
-            hipLaunchKernelGGL((tree_walk_kernel<1, false>), grid, block, 0, stream, a);
-        else
-            hipLaunchKernelGGL((tree_walk_kernel<2, false>), grid, block, 0, stream, a);
+    const int variant = (order == 2 ? 4 : 0) + (t->quadrupole ? 2 : 0) + (a.tv.complete ? 1 : 0);
+    switch (variant) {
+        case 0: hipLaunchKernelGGL((tree_walk_kernel<1, false, false>), grid, block, 0, stream, a); break;
+        case 1: hipLaunchKernelGGL((tree_walk_kernel<1, false, true>), grid, block, 0, stream, a); break;
+        case 2: hipLaunchKernelGGL((tree_walk_kernel<1, true, false>), grid, block, 0, stream, a); break;
+        case 3: hipLaunchKernelGGL((tree_walk_kernel<1, true, true>), grid, block, 0, stream, a); break;
+        case 4: hipLaunchKernelGGL((tree_walk_kernel<2, false, false>), grid, block, 0, stream, a); break;
+        case 5: hipLaunchKernelGGL((tree_walk_kernel<2, false, true>), grid, block, 0, stream, a); break;
+        case 6: hipLaunchKernelGGL((tree_walk_kernel<2, true, false>), grid, block, 0, stream, a); break;
+        default: hipLaunchKernelGGL((tree_walk_kernel<2, true, true>), grid, block, 0, stream, a); break;
     }
     return hip_status(hipGetLastError(), "tree walk");
 }

@@ -206,7 +206,7 @@ struct TableArgs {
     int N, n_tgt;
 };
 
-template <int ORDER, bool POT>
+template <int ORDER, bool POT, bool COMPLETE>
 __global__ __launch_bounds__(kBlock) void forces_table_kernel(TableArgs a) {
     __shared__ SrcRec tile[kBlock];
     const int tid = threadIdx.x;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void forces_table_kernel(TableArgs a) {
             for (int s = 0; s < e; ++s) {
                 const SrcRec src = tile[s0 + s];
                 const bool self = (int64_t)(base + s0 + s) == i;
-                table_pair<ORDER, POT>(a.tv, a.pc, xi, yi, zi, hi, src, self, active, px, py, pz, pp);
+                table_pair<ORDER, POT, COMPLETE>(a.tv, a.pc, xi, yi, zi, hi, src, self, active, px, py, pz, pp);
             }
             kahan_add(sx, cx, px);
             kahan_add(sy, cy, py);
@@ -257,7 +257,10 @@ __global__ __launch_bounds__(kBlock) void forces_table_kernel(TableArgs a) {
 template <int ORDER, bool POT>
 hipError_t launch_t(const TableArgs &a, hipStream_t stream) {
     const int grid = (a.n_tgt + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL((forces_table_kernel<ORDER, POT>), dim3(grid), dim3(kBlock), 0, stream, a);
+    if (a.tv.complete)
+        hipLaunchKernelGGL((forces_table_kernel<ORDER, POT, true>), dim3(grid), dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL((forces_table_kernel<ORDER, POT, false>), dim3(grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

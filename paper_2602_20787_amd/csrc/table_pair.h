@@ -128,7 +128,9 @@ __device__ __forceinline__ void lookup(const TableView &a, float delta, float r,
 // pz += m Fz_eff, pp += m P (the caller negates at the end).  Every lane of
 // the wave must call it together (the exact band beyond a band table's
 // rho_max is shared by the wave); ``active`` marks lanes with a real target.
-template <int ORDER, bool POT>
+// COMPLETE: the table holds every image |n| >= 2 (pairs beyond rho_max take
+// the line-mass limit) rather than a band.
+template <int ORDER, bool POT, bool COMPLETE>
 __device__ __forceinline__ void table_pair(const TableView &a, const PeriodConsts &pc, double xi, double yi,
                                            double zi, float hi, const SrcRec &src, bool self, bool active,
                                            float &px, float &py, float &pz, float &pp) {
@@ -165,7 +167,7 @@ __device__ __forceinline__ void table_pair(const TableView &a, const PeriodConst
         Rz = 0.f;
         Rr = 0.f;
     }
-    if (a.complete) {
+    if (COMPLETE) {
         // line-mass limit of the complete sum minus the three nearest images
         if (!inside && !self) {
             const float ds = d * pc.invLf, r2 = r * r;
@@ -182,7 +184,7 @@ __device__ __forceinline__ void table_pair(const TableView &a, const PeriodConst
             Rr = -2.f * __builtin_amdgcn_rcpf(r) - nr;
         }
     }
-    uint64_t outside = a.complete ? 0 : __ballot(!inside && !self && active);
+    uint64_t outside = COMPLETE ? 0 : __ballot(!inside && !self && active);
     while (outside) {
         const int c = __builtin_ctzll(outside);
         outside &= outside - 1;
