@@ -97,3 +97,19 @@ def test_table_full_size_sampled_matches_oracle(sc, order):
     print(f"order {order}, N=2^20: max rel err vs oracle {err.max():.2e}")
     assert err.max() <= 2e-5
     t.close()
+
+
+@pytest.mark.parametrize("order,complete", [(1, False), (2, True)])
+def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc, order, complete):
+    # a call over all targets walks them in spatial order; each target's sum
+    # is unchanged, so it equals bit for bit the same targets asked for by index
+    p = synth.cylinder_load(9000, seed=44)
+    t = sc.CorrectionTable.ewald(24, 16, 4.0, 2.0, 5, 12) if complete else sc.CorrectionTable(24, 16, 5.0, 1024)
+    pos, m, e = to_dev(p)
+    full, fpot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order)
+    tg = torch.from_numpy(synth.target_sample(p.N, 500, seed=45)).cuda()
+    sub, spot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order, targets=tg)
+    torch.cuda.synchronize()
+    assert torch.equal(full[:, tg], sub)
+    assert torch.equal(fpot[tg], spot)
+    t.close()
