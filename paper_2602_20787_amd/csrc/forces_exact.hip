@@ -43,6 +43,7 @@ constexpr int kSub = 32;     // sources per compensated flush
 struct ExactArgs {
     const double *x, *y, *z, *m, *h;
     const int64_t *targets;  // null: target k is particle k
+    const int *perm;         // all targets in spatial order; outputs go to each target's own index
     float *ax, *ay, *az, *pot;
     double L, invL, halfL;
     ImageConsts c;
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
     const int tid = threadIdx.x;
     const int k = blockIdx.x * kBlock + tid;
     const bool active = k < a.n_tgt;
-    const int64_t i = active ? (a.targets ? a.targets[k] : (int64_t)k) : 0;
+    const int64_t i = active ? (a.perm ? (int64_t)a.perm[k] : (a.targets ? a.targets[k] : (int64_t)k)) : 0;
     const double xi = a.x[i], yi = a.y[i], zi = wrap_z(a.z[i], a.L);
     const float hi = (float)a.h[i];
 
@@ -138,13 +139,12 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
         __syncthreads();
     }
     if (active) {
-        const int n = a.n_tgt;
         // attraction: a = -sum m_j S (x_i - x_j), potential = -sum m_j / r
-        a.ax[k] = -(sx - cx);
-        a.ay[k] = -(sy - cy);
-        a.az[k] = -(sz - cz);
-        if (POT) a.pot[k] = -(sp - cp);
-        (void)n;
+        const int64_t o = a.perm ? i : (int64_t)k;
+        a.ax[o] = -(sx - cx);
+        a.ay[o] = -(sy - cy);
+        a.az[o] = -(sz - cz);
+        if (POT) a.pot[o] = -(sp - cp);
     }
 }
 
@@ -193,12 +193,20 @@ int launch_forces_exact(const double *pos, const double *mass, const double *eps
     a.c.n_img = n_img;
     a.N = (int)N;
     a.n_tgt = (int)n_tgt;
+    a.perm = nullptr;
+    // all targets: walk them in spatial order (scratch is stream-ordered)
+    void *scratch = nullptr;
+    if (!targets && N >= kOrderTargetsMin) {
+        const int rc = order_targets(pos, N, L, stream, &scratch, &a.perm);
+        if (rc) return rc;
+    }
     hipError_t e;
     const bool comp = (mode == STEPS_SUM_COMPENSATED);
     if (out_pot)
         e = comp ? launch_nimg<true, true>(a, stream) : launch_nimg<true, false>(a, stream);
     else
         e = comp ? launch_nimg<false, true>(a, stream) : launch_nimg<false, false>(a, stream);
+    if (scratch) (void)hipFreeAsync(scratch, stream);
     return hip_status(e, "forces_exact launch");
 }
 

@@ -33,8 +33,6 @@
 // per thread like the exact kernel; sources come through LDS tiles, the
 // table through the vector caches.  Pairs of a band table beyond r_max take
 // the exact band, shared by the 64 lanes of the wave.
-#include <hipcub/hipcub.hpp>
-
 #include "table_pair.h"
 
 namespace steps {
@@ -258,42 +256,6 @@ __global__ __launch_bounds__(kBlock) void forces_table_kernel(TableArgs a) {
     }
 }
 
-// Spatial order of the targets (a 30-bit Morton key over the transverse
-// extent and the period): the lanes of a wave then look up nearby table
-// cells for each source, which keeps the table gathers in the vector cache.
-// The order changes no result (each target's sum runs over the sources in
-// their own order).
-__global__ void extent_kernel(const double *pos, int N, double *partial) {
-    __shared__ double m[256];
-    double v = 0.0;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256)
-        v = fmax(v, fmax(fabs(pos[i]), fabs(pos[N + i])));
-    m[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) m[threadIdx.x] = fmax(m[threadIdx.x], m[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = m[0];
-}
-
-__global__ void order_keys_kernel(const double *pos, int N, double L, const double *partial, int n_partial,
-                                  uint32_t *key, int *idx) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    double ext = 0.0;
-    for (int b = 0; b < n_partial; ++b) ext = fmax(ext, partial[b]);
-    const double sc = ext > 0.0 ? 1024.0 / (2.0 * ext) : 0.0;
-    const double zw = wrap_z(pos[2 * N + i], L);
-    const uint32_t q[3] = {(uint32_t)min(1023.0, fmax(0.0, floor((pos[i] + ext) * sc))),
-                           (uint32_t)min(1023.0, fmax(0.0, floor((pos[N + i] + ext) * sc))),
-                           (uint32_t)min(1023.0, fmax(0.0, floor(zw / L * 1024.0)))};
-    uint32_t k = 0;
-    for (int b = 0; b < 10; ++b)
-        k |= (((q[0] >> b) & 1u) << (3 * b + 2)) | (((q[1] >> b) & 1u) << (3 * b + 1)) | (((q[2] >> b) & 1u) << (3 * b));
-    key[i] = k;
-    idx[i] = i;
-}
 
 template <int ORDER, bool POT>
 hipError_t launch_t(const TableArgs &a, hipStream_t stream) {
@@ -456,30 +418,8 @@ STEPS_API int steps_cyl_forces_table(const double *pos, const double *mass, cons
     a.perm = nullptr;
     // all targets: walk them in spatial order (scratch is stream-ordered)
     void *scratch = nullptr;
-    if (!targets && N >= 4096) {
-        const int n = (int)N, nb = 64;
-        size_t cub = 0;
-        STEPS_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, cub, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                                           (int *)nullptr, (int *)nullptr, n, 0, 30, stream));
-        const size_t bytes = (size_t)16 * n + 8 * nb + 256 + cub;  // keys, indices (twice), partials, sort
-        STEPS_CHECK_HIP(hipMallocAsync(&scratch, bytes, stream));
-        char *p = (char *)scratch;
-        double *partial = (double *)p;
-        p += 8 * (size_t)nb;
-        uint32_t *k_in = (uint32_t *)p, *k_out = k_in + n;
-        int *i_in = (int *)(k_out + n), *i_out = i_in + n;
-        void *tmp = (void *)(((uintptr_t)(i_out + n) + 255) & ~(uintptr_t)255);
-        hipLaunchKernelGGL(extent_kernel, dim3(nb), dim3(256), 0, stream, pos, n, partial);
-        hipLaunchKernelGGL(order_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, pos, n, L, partial, nb,
-                           k_in, i_in);
-        hipError_t e0 = hipGetLastError();
-        if (e0 == hipSuccess)
-            e0 = hipcub::DeviceRadixSort::SortPairs(tmp, cub, k_in, k_out, i_in, i_out, n, 0, 30, stream);
-        if (e0 != hipSuccess) {
-            (void)hipFreeAsync(scratch, stream);
-            return hip_status(e0, "target order");
-        }
-        a.perm = i_out;
+    if (!targets && N >= kOrderTargetsMin) {
+        if ((rc = order_targets(pos, N, L, stream, &scratch, &a.perm))) return rc;
     }
     hipError_t e;
     if (order == 1)

@@ -206,3 +206,16 @@ def test_config3_full_size_sampled_and_momentum(sc):
     scale = np.sum(p.mass * np.linalg.norm(a, axis=0))
     print(f"C3 |sum m a| / sum m|a| = {mom.max() / scale:.3e}")
     assert mom.max() <= 1e-5 * scale
+
+
+def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc):
+    # a call over all targets walks them in spatial order; each target's sum
+    # is unchanged, so it equals bit for bit the same targets asked for by index
+    p = synth.clustered_load(12000, n_clumps=8, clump_frac=0.02, seed=46)
+    pos, m, e = (torch.from_numpy(x).cuda() for x in (p.pos, p.mass, p.eps))
+    full, fpot = sc.steps_cyl_forces(pos, m, e, p.L, 8)
+    tg = torch.from_numpy(synth.target_sample(p.N, 700, seed=47)).cuda()
+    sub, spot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=tg)
+    torch.cuda.synchronize()
+    assert torch.equal(full[:, tg], sub)
+    assert torch.equal(fpot[tg], spot)
