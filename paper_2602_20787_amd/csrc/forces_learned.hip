@@ -35,6 +35,7 @@ constexpr int kSub = 32;        // sources per compensated flush
 struct LearnedArgs {
     const double *x, *y, *z, *m, *h;
     const int64_t *targets;
+    const int *perm;  // all targets in spatial order; outputs go to each target's own index
     const mlp::Packed *P;
     float *ax, *ay, *az, *pot;
     double L, invL, halfL;
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
     const int col = lane & 31, h = lane >> 5;
     const int k = blockIdx.x * kTargets + wave * 32 + col;
     const bool active = k < a.n_tgt;
-    const int64_t i = active ? (a.targets ? a.targets[k] : (int64_t)k) : 0;
+    const int64_t i = active ? (a.perm ? (int64_t)a.perm[k] : (a.targets ? a.targets[k] : (int64_t)k)) : 0;
     const double xi = a.x[i], yi = a.y[i], zi = wrap_z(a.z[i], a.L);
     const float hi = (float)a.h[i];
 
@@ -222,10 +223,11 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
     const float ox = __shfl_xor(sx - cx, 32), oy = __shfl_xor(sy - cy, 32);
     const float oz = __shfl_xor(sz - cz, 32), op = __shfl_xor(sp - cp, 32);
     if (active && h == 0) {
-        a.ax[k] = -((sx - cx) + ox);
-        a.ay[k] = -((sy - cy) + oy);
-        a.az[k] = -((sz - cz) + oz);
-        if (POT) a.pot[k] = -((sp - cp) + op);
+        const int64_t o = a.perm ? i : (int64_t)k;
+        a.ax[o] = -((sx - cx) + ox);
+        a.ay[o] = -((sy - cy) + oy);
+        a.az[o] = -((sz - cz) + oz);
+        if (POT) a.pot[o] = -((sp - cp) + op);
     }
 }
 
@@ -268,12 +270,20 @@ int launch_forces_learned(const double *pos, const double *mass, const double *e
     a.c.n_img = 1;
     a.N = (int)N;
     a.n_tgt = (int)n_tgt;
+    a.perm = nullptr;
+    // all targets: walk them in spatial order (scratch is stream-ordered)
+    void *scratch = nullptr;
+    if (!targets && N >= kOrderTargetsMin) {
+        const int rc = order_targets(pos, N, L, stream, &scratch, &a.perm);
+        if (rc) return rc;
+    }
     const bool comp = (mode == STEPS_SUM_COMPENSATED);
     hipError_t e;
     if (out_pot)
         e = comp ? launch_t<true, true>(a, stream) : launch_t<true, false>(a, stream);
     else
         e = comp ? launch_t<false, true>(a, stream) : launch_t<false, false>(a, stream);
+    if (scratch) (void)hipFreeAsync(scratch, stream);
     return hip_status(e, "forces_learned launch");
 }
 

@@ -105,3 +105,14 @@ def test_learned_ragged_and_plain(sc, net):
     ref = om.forces_learned(p.pos, p.mass, p.eps, p.L, net.params().astype(np.float64))
     assert rel_err(acc_c, ref).max() <= TOL
     assert rel_err(acc_p, ref).max() <= TOL
+
+
+def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc, net):
+    p = synth.cylinder_load(9000, seed=48)
+    pos, m, e = (torch.from_numpy(x).cuda() for x in (p.pos, p.mass, p.eps))
+    full, fpot = sc.steps_cyl_forces_learned(pos, m, e, p.L, net)
+    tg = torch.from_numpy(synth.target_sample(p.N, 400, seed=49)).cuda()
+    sub, spot = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=tg)
+    torch.cuda.synchronize()
+    assert torch.equal(full[:, tg], sub)
+    assert torch.equal(fpot[tg], spot)
