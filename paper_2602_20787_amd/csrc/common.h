@@ -26,12 +26,14 @@ int hip_status(hipError_t e, const char *what);
 
 inline bool finite_positive(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Targets 0..N-1 in spatial order (see target_order.hip): *perm points into
+// The positions 0..n_tgt-1 of a target list (targets, or 0..N-1 when NULL)
+// in spatial order of the targets (see target_order.hip): *perm points into
 // stream-ordered scratch that the caller releases with hipFreeAsync after
 // the launches that read it.  STEPS_OK or an error status.
-int order_targets(const double *pos, int64_t N, double L, hipStream_t stream, void **scratch, const int **perm);
+int order_targets(const double *pos, int64_t N, double L, const int64_t *targets, int64_t n_tgt, hipStream_t stream,
+                  void **scratch, const int **perm);
 
-// all-target calls at least this large are walked in spatial order
+// target lists at least this long are walked in spatial order
 constexpr int64_t kOrderTargetsMin = 4096;
 
 }  // namespace steps

@@ -43,7 +43,7 @@ constexpr int kSub = 32;     // sources per compensated flush
 struct ExactArgs {
     const double *x, *y, *z, *m, *h;
     const int64_t *targets;  // null: target k is particle k
-    const int *perm;         // all targets in spatial order; outputs go to each target's own index
+    const int *perm;         // list positions in spatial order of their targets, or null
     float *ax, *ay, *az, *pot;
     double L, invL, halfL;
     ImageConsts c;
@@ -56,7 +56,8 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
     const int tid = threadIdx.x;
     const int k = blockIdx.x * kBlock + tid;
     const bool active = k < a.n_tgt;
-    const int64_t i = active ? (a.perm ? (int64_t)a.perm[k] : (a.targets ? a.targets[k] : (int64_t)k)) : 0;
+    const int64_t kk = active ? (a.perm ? (int64_t)a.perm[k] : (int64_t)k) : 0;  // position in the list
+    const int64_t i = a.targets ? a.targets[kk] : kk;
     const double xi = a.x[i], yi = a.y[i], zi = wrap_z(a.z[i], a.L);
     const float hi = (float)a.h[i];
 
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
     }
     if (active) {
         // attraction: a = -sum m_j S (x_i - x_j), potential = -sum m_j / r
-        const int64_t o = a.perm ? i : (int64_t)k;
+        const int64_t o = kk;
         a.ax[o] = -(sx - cx);
         a.ay[o] = -(sy - cy);
         a.az[o] = -(sz - cz);
@@ -194,10 +195,10 @@ int launch_forces_exact(const double *pos, const double *mass, const double *eps
     a.N = (int)N;
     a.n_tgt = (int)n_tgt;
     a.perm = nullptr;
-    // all targets: walk them in spatial order (scratch is stream-ordered)
+    // walk the targets in spatial order (scratch is stream-ordered)
     void *scratch = nullptr;
-    if (!targets && N >= kOrderTargetsMin) {
-        const int rc = order_targets(pos, N, L, stream, &scratch, &a.perm);
+    if (n_tgt >= kOrderTargetsMin) {
+        const int rc = order_targets(pos, N, L, targets, n_tgt, stream, &scratch, &a.perm);
         if (rc) return rc;
     }
     hipError_t e;

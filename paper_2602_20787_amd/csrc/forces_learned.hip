@@ -35,7 +35,7 @@ constexpr int kSub = 32;        // sources per compensated flush
 struct LearnedArgs {
     const double *x, *y, *z, *m, *h;
     const int64_t *targets;
-    const int *perm;  // all targets in spatial order; outputs go to each target's own index
+    const int *perm;  // list positions in spatial order of their targets, or null
     const mlp::Packed *P;
     float *ax, *ay, *az, *pot;
     double L, invL, halfL;
@@ -129,7 +129,8 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
     const int col = lane & 31, h = lane >> 5;
     const int k = blockIdx.x * kTargets + wave * 32 + col;
     const bool active = k < a.n_tgt;
-    const int64_t i = active ? (a.perm ? (int64_t)a.perm[k] : (a.targets ? a.targets[k] : (int64_t)k)) : 0;
+    const int64_t kk = active ? (a.perm ? (int64_t)a.perm[k] : (int64_t)k) : 0;  // position in the list
+    const int64_t i = a.targets ? a.targets[kk] : kk;
     const double xi = a.x[i], yi = a.y[i], zi = wrap_z(a.z[i], a.L);
     const float hi = (float)a.h[i];
 
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
     const float ox = __shfl_xor(sx - cx, 32), oy = __shfl_xor(sy - cy, 32);
     const float oz = __shfl_xor(sz - cz, 32), op = __shfl_xor(sp - cp, 32);
     if (active && h == 0) {
-        const int64_t o = a.perm ? i : (int64_t)k;
+        const int64_t o = kk;
         a.ax[o] = -((sx - cx) + ox);
         a.ay[o] = -((sy - cy) + oy);
         a.az[o] = -((sz - cz) + oz);
@@ -271,10 +272,10 @@ int launch_forces_learned(const double *pos, const double *mass, const double *e
     a.N = (int)N;
     a.n_tgt = (int)n_tgt;
     a.perm = nullptr;
-    // all targets: walk them in spatial order (scratch is stream-ordered)
+    // walk the targets in spatial order (scratch is stream-ordered)
     void *scratch = nullptr;
-    if (!targets && N >= kOrderTargetsMin) {
-        const int rc = order_targets(pos, N, L, stream, &scratch, &a.perm);
+    if (n_tgt >= kOrderTargetsMin) {
+        const int rc = order_targets(pos, N, L, targets, n_tgt, stream, &scratch, &a.perm);
         if (rc) return rc;
     }
     const bool comp = (mode == STEPS_SUM_COMPENSATED);

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(64) void build_ewald_kernel(float2 *nodes, double2 
 struct TableArgs {
     const double *x, *y, *z, *m, *h;
     const int64_t *targets;
-    const int *perm;  // all targets in spatial order; outputs go to each target's own index
+    const int *perm;  // list positions in spatial order of their targets, or null
     float *ax, *ay, *az, *pot;
     TableView tv;
     PeriodConsts pc;
@@ -214,7 +214,8 @@ __global__ __launch_bounds__(kBlock) void forces_table_kernel(TableArgs a) {
     const int lane = tid & 63;
     const int k = blockIdx.x * kBlock + tid;
     const bool active = k < a.n_tgt;
-    const int64_t i = active ? (a.perm ? (int64_t)a.perm[k] : (a.targets ? a.targets[k] : (int64_t)k)) : 0;
+    const int64_t kk = active ? (a.perm ? (int64_t)a.perm[k] : (int64_t)k) : 0;  // position in the list
+    const int64_t i = a.targets ? a.targets[kk] : kk;
     const double xi = a.x[i], yi = a.y[i], zi = wrap_z(a.z[i], a.pc.L);
     const float hi = (float)a.h[i];
     float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void forces_table_kernel(TableArgs a) {
         }
     }
     if (active) {
-        const int64_t o = a.perm ? i : (int64_t)k;
+        const int64_t o = kk;
         a.ax[o] = -(sx - cx);
         a.ay[o] = -(sy - cy);
         a.az[o] = -(sz - cz);
@@ -416,10 +417,10 @@ STEPS_API int steps_cyl_forces_table(const double *pos, const double *mass, cons
     a.N = (int)N;
     a.n_tgt = (int)n_targets;
     a.perm = nullptr;
-    // all targets: walk them in spatial order (scratch is stream-ordered)
+    // walk the targets in spatial order (scratch is stream-ordered)
     void *scratch = nullptr;
-    if (!targets && N >= kOrderTargetsMin) {
-        if ((rc = order_targets(pos, N, L, stream, &scratch, &a.perm))) return rc;
+    if (n_targets >= kOrderTargetsMin) {
+        if ((rc = order_targets(pos, N, L, targets, n_targets, stream, &scratch, &a.perm))) return rc;
     }
     hipError_t e;
     if (order == 1)

@@ -1,10 +1,10 @@
-// Spatial order of all targets, shared by the force kernels that take every
-// particle as a target: a 30-bit Morton key of (x, y) over the transverse
-// extent and of z over the period, radix-sorted.  Neighbouring lanes then
+// Spatial order of the targets, shared by the force kernels: a 30-bit
+// Morton key of (x, y) over the transverse extent and of z over the period,
+// radix-sorted together with the targets' positions in the caller's list.  Neighbouring lanes then
 // hold neighbouring targets, which keeps data-dependent work (table gathers,
 // the softened branch) coherent within a wave.  The order changes no result:
 // each target's sum runs over the sources in their own order and is written
-// to the target's own index.
+// to the target's own position in the list.
 #include <hipcub/hipcub.hpp>
 
 #include "common.h"
@@ -29,10 +29,11 @@ __global__ void extent_kernel(const double *pos, int N, double *partial) {
     if (threadIdx.x == 0) partial[blockIdx.x] = m[0];
 }
 
-__global__ void order_keys_kernel(const double *pos, int N, double L, const double *partial, uint32_t *key,
-                                  int *idx) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+__global__ void order_keys_kernel(const double *pos, int N, double L, const double *partial, const int64_t *targets,
+                                  int n_tgt, uint32_t *key, int *idx) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_tgt) return;
+    const int64_t i = targets ? targets[k] : (int64_t)k;
     double ext = 0.0;
     for (int b = 0; b < kExtentBlocks; ++b) ext = fmax(ext, partial[b]);
     const double sc = ext > 0.0 ? 1024.0 / (2.0 * ext) : 0.0;
@@ -40,19 +41,21 @@ __global__ void order_keys_kernel(const double *pos, int N, double L, const doub
     const uint32_t q[3] = {(uint32_t)fmin(1023.0, fmax(0.0, floor((pos[i] + ext) * sc))),
                            (uint32_t)fmin(1023.0, fmax(0.0, floor((pos[N + i] + ext) * sc))),
                            (uint32_t)fmin(1023.0, fmax(0.0, floor(zw / L * 1024.0)))};
-    uint32_t k = 0;
+    uint32_t code = 0;
     for (int b = 0; b < 10; ++b)
-        k |= (((q[0] >> b) & 1u) << (3 * b + 2)) | (((q[1] >> b) & 1u) << (3 * b + 1)) | (((q[2] >> b) & 1u) << (3 * b));
-    key[i] = k;
-    idx[i] = i;
+        code |= (((q[0] >> b) & 1u) << (3 * b + 2)) | (((q[1] >> b) & 1u) << (3 * b + 1)) |
+                (((q[2] >> b) & 1u) << (3 * b));
+    key[k] = code;
+    idx[k] = k;
 }
 
 }  // namespace
 
-int order_targets(const double *pos, int64_t N, double L, hipStream_t stream, void **scratch, const int **perm) {
+int order_targets(const double *pos, int64_t N, double L, const int64_t *targets, int64_t n_tgt, hipStream_t stream,
+                  void **scratch, const int **perm) {
     *scratch = nullptr;
     *perm = nullptr;
-    const int n = (int)N;
+    const int n = (int)n_tgt;
     size_t cub = 0;
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, cub, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                       (int *)nullptr, (int *)nullptr, n, 0, 30, stream);
@@ -68,9 +71,9 @@ int order_targets(const double *pos, int64_t N, double L, hipStream_t stream, vo
     uint32_t *k_in = (uint32_t *)(p + 8 * kExtentBlocks), *k_out = k_in + n;
     int *i_in = (int *)(k_out + n), *i_out = i_in + n;
     void *tmp = (void *)(((uintptr_t)(i_out + n) + 255) & ~(uintptr_t)255);
-    hipLaunchKernelGGL(extent_kernel, dim3(kExtentBlocks), dim3(256), 0, stream, pos, n, partial);
-    hipLaunchKernelGGL(order_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, pos, n, L, partial, k_in,
-                       i_in);
+    hipLaunchKernelGGL(extent_kernel, dim3(kExtentBlocks), dim3(256), 0, stream, pos, (int)N, partial);
+    hipLaunchKernelGGL(order_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, pos, (int)N, L, partial,
+                       targets, n, k_in, i_in);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortPairs(tmp, cub, k_in, k_out, i_in, i_out, n, 0, 30, stream);
     if (e != hipSuccess) {

@@ -219,3 +219,17 @@ def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc):
     torch.cuda.synchronize()
     assert torch.equal(full[:, tg], sub)
     assert torch.equal(fpot[tg], spot)
+
+
+def test_long_target_lists_in_spatial_order_are_bitwise_exact(sc):
+    # lists of at least 4096 targets are walked in spatial order too; duplicates
+    # and any order give, per list position, the full call's result bit for bit
+    p = synth.clustered_load(12000, n_clumps=8, clump_frac=0.02, seed=50)
+    pos, m, e = to_dev(p)
+    full, fpot = sc.steps_cyl_forces(pos, m, e, p.L, 8)
+    rng = np.random.default_rng(51)
+    tg = torch.from_numpy(rng.integers(0, p.N, 6000)).cuda()
+    sub, spot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=tg)
+    torch.cuda.synchronize()
+    assert torch.equal(full[:, tg], sub)
+    assert torch.equal(fpot[tg], spot)

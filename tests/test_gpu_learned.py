@@ -116,3 +116,15 @@ def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc, net):
     torch.cuda.synchronize()
     assert torch.equal(full[:, tg], sub)
     assert torch.equal(fpot[tg], spot)
+
+
+def test_long_target_lists_in_spatial_order_are_bitwise_exact(sc, net):
+    p = synth.cylinder_load(9000, seed=55)
+    pos, m, e = (torch.from_numpy(x).cuda() for x in (p.pos, p.mass, p.eps))
+    full, fpot = sc.steps_cyl_forces_learned(pos, m, e, p.L, net)
+    rng = np.random.default_rng(56)
+    tg = torch.from_numpy(rng.integers(0, p.N, 5000)).cuda()
+    sub, spot = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=tg)
+    torch.cuda.synchronize()
+    assert torch.equal(full[:, tg], sub)
+    assert torch.equal(fpot[tg], spot)

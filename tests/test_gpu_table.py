@@ -113,3 +113,17 @@ def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc, order, 
     assert torch.equal(full[:, tg], sub)
     assert torch.equal(fpot[tg], spot)
     t.close()
+
+
+def test_long_target_lists_in_spatial_order_are_bitwise_exact(sc):
+    p = synth.cylinder_load(9000, seed=53)
+    t = sc.CorrectionTable(24, 16, 5.0, 1024)
+    pos, m, e = to_dev(p)
+    full, fpot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=1)
+    rng = np.random.default_rng(54)
+    tg = torch.from_numpy(rng.integers(0, p.N, 5000)).cuda()
+    sub, spot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=1, targets=tg)
+    torch.cuda.synchronize()
+    assert torch.equal(full[:, tg], sub)
+    assert torch.equal(fpot[tg], spot)
+    t.close()
