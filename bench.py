@@ -391,7 +391,7 @@ def main():
                     help="also run a 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU (--gpus 1); sharding over GPUs is designed, not implemented"}))
         sys.exit(2)
 
     import numpy as np
