@@ -36,8 +36,8 @@ PEAK_FP32_UNPACKED = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter
 # reads for a 256 MiB copy (profiles/forces_exact_N1M_nimg8_counters.md).
 # Valid only for the kernel sources they were measured on (hash below).
-TRAFFIC_EXACT_N1M = {"bytes": 5.9794e+09, "fetch_scale": 1.99971, "write_scale": 1.0,
-                     "sources_sha256_16": "89faf01c7ce22b3f"}
+TRAFFIC_EXACT_N1M = {"bytes": 5.9784e+09, "fetch_scale": 1.99972, "write_scale": 1.0,
+                     "sources_sha256_16": "32b321b84eac9e14"}
 TRAFFIC_SOURCES = ["forces_exact.hip", "pair_fp32.h", "pair_f64.h", "target_order.hip"]
 
 
