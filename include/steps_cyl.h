@@ -26,6 +26,15 @@
  *    z - L floor(z/L) before use.  Outputs are caller-owned device arrays.
  *    The library never frees caller memory and allocates nothing per call
  *    except where an entry point says otherwise.
+ *  - Target order: with 4096 or more targets, the direct entry points
+ *    (steps_cyl_forces[_ex], steps_cyl_forces_learned[_ex],
+ *    steps_cyl_forces_table) first sort the targets by a 30-bit Morton key
+ *    of (x, y, z) so that each workgroup holds neighbours; every output stays
+ *    at its target's position and every target's result is bitwise that of
+ *    the unsorted walk.  The keys live in stream-ordered scratch
+ *    (hipMallocAsync on `stream`, about 16 bytes per target plus the radix
+ *    sort's temporary storage, released with hipFreeAsync on the same
+ *    stream); STEPS_ENOMEM if it cannot be had.
  *  - Every call is asynchronous on `stream` (0 = the null stream); results
  *    are valid after the stream is synchronised.  Argument errors are found
  *    on the host before any device work and return a negative status; the

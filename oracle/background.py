@@ -44,8 +44,10 @@ import oracle
 
 # ---------------------------------------------------------------- F_h
 def _w(rho, R, Y):
+    # w- = R^2 + rho^2 - 2 rho c written without cancellation:
+    # (R - rho)^2 + 2 rho (R - c), with R - c = Y^2 / (R + c)
     c = math.sqrt(max(R * R - Y * Y, 0.0))
-    return R * R + rho * rho + 2.0 * rho * c, R * R + rho * rho - 2.0 * rho * c
+    return R * R + rho * rho + 2.0 * rho * c, (R - rho) ** 2 + 2.0 * rho * Y * Y / (R + c)
 
 
 def cylinder_field(rho, R, Z, rho0, G=1.0):
@@ -63,10 +65,18 @@ def cylinder_field(rho, R, Z, rho0, G=1.0):
         wp, wm = _w(rho, R, Y)
         return math.log(wp / wm)
 
-    brk = [0.0] if abs(rho - R) < 1e-12 else None
     # the end-cap term vanishes for an infinite cylinder (Z -> inf)
     A = 0.0 if math.isinf(Z) else integrate.quad(fa, 0.0, R, epsabs=1e-15, epsrel=1e-12, limit=400)[0]
-    B, _ = integrate.quad(fb, 0.0, R, epsabs=1e-15, epsrel=1e-12, limit=400, points=brk)
+    if rho == R:
+        # on the mantle w- = Y^2 2R / (R + c): take the log singularity out,
+        # int_0^R -2 ln Y dY = -2 (R ln R - R)
+        def fs(Y):
+            c = math.sqrt(max(R * R - Y * Y, 0.0))
+            return math.log((R * R + rho * rho + 2.0 * rho * c) * (R + c) / (2.0 * R))
+
+        B = integrate.quad(fs, 0.0, R, epsabs=1e-15, epsrel=1e-12, limit=400)[0] - 2.0 * (R * math.log(R) - R)
+    else:
+        B = integrate.quad(fb, 0.0, R, epsabs=1e-15, epsrel=1e-12, limit=400)[0]
     return 2.0 * G * rho0 * (2.0 * A - B)
 
 
