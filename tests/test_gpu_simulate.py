@@ -36,3 +36,17 @@ def test_driver_runs_each_mode(sim, capsys, mode, med, err, pz):
     assert last["median_rel_err"] <= med
     assert last["max_rel_err"] <= err
     assert summary["max_pz_ratio"] <= pz
+
+
+@pytest.mark.parametrize("argv", [["--path", "exact", "--targets", "1000", "--potential"],
+                                  ["--path", "learned", "--targets", "4096"],
+                                  ["--path", "table", "--order", "2"],
+                                  ["--path", "tree", "--quadrupole"]])
+def test_profiling_driver_runs_each_path(capsys, argv):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_20787_amd import run_kernel
+    run_kernel.main(argv + ["--N", "8192", "--reps", "2"])
+    row = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert row["path"] == argv[1] and row["N"] == 8192 and len(row["ms"]) == 2
+    assert all(ms > 0 for ms in row["ms"])
