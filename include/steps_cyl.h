@@ -26,12 +26,12 @@
  *    z - L floor(z/L) before use.  Outputs are caller-owned device arrays.
  *    The library never frees caller memory and allocates nothing per call
  *    except where an entry point says otherwise.
- *  - Target order: with 4096 or more targets, the direct entry points
- *    (steps_cyl_forces[_ex], steps_cyl_forces_learned[_ex],
- *    steps_cyl_forces_table) first sort the targets by a 30-bit Morton key
- *    of (x, y, z) so that each workgroup holds neighbours; every output stays
- *    at its target's position and every target's result is bitwise that of
- *    the unsorted walk.  The keys live in stream-ordered scratch
+ *  - Target order: with 4096 or more targets, the per-target entry points
+ *    (steps_cyl_forces_ex in its per-target modes,
+ *    steps_cyl_forces_learned[_ex], steps_cyl_forces_table) first sort the
+ *    targets by a 30-bit Morton key of (x, y, z) so that each workgroup holds
+ *    neighbours; every output stays at its target's position and every
+ *    target's result is bitwise that of the unsorted walk.  The keys live in stream-ordered scratch
  *    (hipMallocAsync on `stream`, about 16 bytes per target plus the radix
  *    sort's temporary storage, released with hipFreeAsync on the same
  *    stream); STEPS_ENOMEM if it cannot be had.
@@ -69,6 +69,7 @@ typedef enum {
 /* Summation modes of steps_cyl_forces_ex. */
 #define STEPS_SUM_COMPENSATED 0   /* FP32 pairs, Kahan-compensated per-target sums */
 #define STEPS_SUM_PLAIN       1   /* FP32 pairs, plain FP32 per-target sums        */
+#define STEPS_SUM_PAIRWISE    2   /* every unordered pair once, all targets only   */
 
 /*
  * steps_cyl_forces -- exact image-sum accelerations (and potentials) of all N
@@ -85,9 +86,19 @@ typedef enum {
  *   out_pot  device, N floats, written; or NULL to skip the potential
  *   stream   HIP stream
  *
- * Arithmetic: pair separations and the z wrap in FP64, then FP32 pair terms
- * and Kahan-compensated FP32 per-target sums.  Returns STEPS_OK, or
- * STEPS_EINVAL / STEPS_EHIP.
+ * Every unordered pair is evaluated once and applied to both particles: the
+ * pair term is odd in the separation (the image set of (j, i) is the negated
+ * set of (i, j)), so the reaction is the action with dx, dy and F_z negated
+ * (F_z keeps its sign where both particles take the minimum image -L/2).
+ * Arithmetic: pair separations and the z wrap in FP64, FP32 pair terms,
+ * FP64 sums.  The sums meet through atomic additions whose order varies from
+ * run to run, so repeated calls agree to one FP32 rounding step, not bit for
+ * bit (steps_cyl_forces_ex with STEPS_SUM_COMPENSATED is the bitwise
+ * deterministic per-target path).  Total momentum is conserved to the
+ * rounding of the sums.  Scratch is stream-ordered (hipMallocAsync on
+ * `stream`, released on it): about 80 bytes per particle plus the radix
+ * sort's temporary storage.  Returns STEPS_OK, or STEPS_EINVAL /
+ * STEPS_ENOMEM / STEPS_EHIP.
  */
 int steps_cyl_forces(const double *pos, const double *mass, const double *eps,
                      int64_t N, double L, int n_img,
@@ -100,7 +111,11 @@ int steps_cyl_forces(const double *pos, const double *mass, const double *eps,
  *   targets    device, n_targets int64 indices in [0, N) (repeats allowed),
  *              or NULL for every particle (then n_targets must equal N)
  *   n_targets  number of targets, >= 1
- *   mode       STEPS_SUM_COMPENSATED or STEPS_SUM_PLAIN
+ *   mode       STEPS_SUM_COMPENSATED (one thread per target, FP32 pair
+ *              terms, Kahan-compensated FP32 sums, bitwise deterministic),
+ *              STEPS_SUM_PLAIN (the same with plain FP32 sums), or
+ *              STEPS_SUM_PAIRWISE (the path of steps_cyl_forces; targets
+ *              must be NULL, else STEPS_EINVAL)
  *   out_acc    device, 3 * n_targets floats, SoA by target position k
  *   out_pot    device, n_targets floats or NULL
  *

@@ -8,7 +8,8 @@ Each path is called once untimed (so that one-time work such as building a
 table stays out of the profile's view of the repetitions) and then --reps
 times, timed with HIP events on the stream it runs on.  Paths:
 
-* ``exact``    steps_cyl_forces_ex with images |n| <= --n-img
+* ``exact``    steps_cyl_forces_ex with images |n| <= --n-img (--pairwise:
+               every unordered pair once, STEPS_SUM_PAIRWISE; all targets)
 * ``learned``  steps_cyl_forces_learned_ex with the shipped network
 * ``table``    steps_cyl_forces_table with the 144 x 128 band table
                2 <= |n| <= 1024 (CIC or TSC, --order)
@@ -42,6 +43,7 @@ def main(argv=None):
     ap.add_argument("--targets", type=int, default=0, help="first K particles as targets (0: all)")
     ap.add_argument("--n-img", type=int, default=8)
     ap.add_argument("--potential", action="store_true")
+    ap.add_argument("--pairwise", action="store_true")
     ap.add_argument("--order", type=int, choices=[1, 2], default=1)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--quadrupole", action="store_true")
@@ -67,8 +69,10 @@ def main(argv=None):
     out = torch.empty((3, K), dtype=torch.float32, device=dev)
 
     if args.path == "exact":
+        mode = sc.STEPS_SUM_PAIRWISE if args.pairwise else sc.STEPS_SUM_COMPENSATED
+
         def call():
-            sc.steps_cyl_forces_ex(pos, m, e, p.L, args.n_img, targets=tg, out_acc=out,
+            sc.steps_cyl_forces_ex(pos, m, e, p.L, args.n_img, targets=tg, mode=mode, out_acc=out,
                                    potential=args.potential, stream=stream)
     elif args.path == "learned":
         net = sc.Mlp.load(NET)
@@ -113,6 +117,8 @@ def main(argv=None):
         row["G_pairs_per_s"] = round(float(K) * N / (float(np.median(ms)) * 1e-3) / 1e9, 3)
     if args.path == "table":
         row["order"] = args.order
+    if args.path == "exact":
+        row.update({"n_img": args.n_img, "pairwise": args.pairwise, "potential": args.potential})
     print(json.dumps(row), flush=True)
 
 

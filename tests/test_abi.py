@@ -250,3 +250,8 @@ def test_tree_calls_reject_bad_arguments():
     assert L.steps_cyl_tree_cells(None, None, None, None, None, None, None, None, None) == sc.STEPS_EINVAL
     L.steps_cyl_tree_destroy(t)
     L.steps_cyl_tree_destroy(None)
+
+
+def test_pairwise_mode_needs_every_particle():
+    rc = sc.lib().steps_cyl_forces_ex(P, P, P, 10, 1.0, 8, P, 10, sc.STEPS_SUM_PAIRWISE, P, None, None)
+    assert rc == sc.STEPS_EINVAL and "targets NULL" in sc.steps_cyl_last_error()

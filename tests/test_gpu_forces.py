@@ -1,4 +1,6 @@
-"""GPU parity of the exact image-sum kernels against the FP64 oracle.
+"""GPU parity of the exact image-sum kernels against the FP64 oracle: the
+pairwise path of steps_cyl_forces and the per-target (one-sided) kernel of
+steps_cyl_forces_ex.
 
 Bar (stated for the exact path): max over targets of |a_gpu - a_ref| / |a_ref|
 <= 1e-5 for the compensated FP32 kernel, and the same relative bound on the
@@ -46,17 +48,23 @@ def pot_err(p_gpu, p_ref):
     return np.abs(p_gpu.detach().cpu().numpy().astype(np.float64) - p_ref) / np.abs(p_ref)
 
 
-def run(sc, p, n_img, **kw):
+def run(sc, p, n_img, one_sided=False, **kw):
+    """steps_cyl_forces (every unordered pair once), or with ``one_sided``
+    the per-target kernel over all targets (steps_cyl_forces_ex)."""
     pos, m, e = to_dev(p)
-    print(f"[case] N={p.N} n_img={n_img} {kw}", flush=True)
-    acc, pot = sc.steps_cyl_forces(pos, m, e, p.L, n_img, **kw)
+    print(f"[case] N={p.N} n_img={n_img} one_sided={one_sided} {kw}", flush=True)
+    if one_sided:
+        acc, pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, n_img, **kw)
+    else:
+        acc, pot = sc.steps_cyl_forces(pos, m, e, p.L, n_img, **kw)
     torch.cuda.synchronize()
     return acc, pot
 
 
-def test_config1_all_targets(sc):
+@pytest.mark.parametrize("one_sided", [False, True])
+def test_config1_all_targets(sc, one_sided):
     p = synth.cylinder_load(4096, seed=0)
-    acc, pot = run(sc, p, 8)
+    acc, pot = run(sc, p, 8, one_sided)
     a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8)
     e = rel_err(acc, a_ref)
     print(f"C1: max {e.max():.3e} rms {math.sqrt(np.mean(e**2)):.3e}")
@@ -64,10 +72,11 @@ def test_config1_all_targets(sc):
     assert pot_err(pot, p_ref).max() <= TOL_POT
 
 
+@pytest.mark.parametrize("one_sided", [False, True])
 @pytest.mark.parametrize("N", [1, 2, 3, 255, 256, 257, 1000, 4099])
-def test_ragged_sizes(sc, N):
+def test_ragged_sizes(sc, N, one_sided):
     p = synth.cylinder_load(N, seed=N)
-    acc, pot = run(sc, p, 8)
+    acc, pot = run(sc, p, 8, one_sided)
     a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8)
     if N == 1:
         assert torch.all(acc == 0) and torch.all(pot == 0)
@@ -76,11 +85,12 @@ def test_ragged_sizes(sc, N):
     assert pot_err(pot, p_ref).max() <= TOL_POT
 
 
+@pytest.mark.parametrize("one_sided", [False, True])
 @pytest.mark.parametrize("n_img", [0, 1, 2, 3, 4, 5, 8, 16, 64])
-def test_image_counts(sc, n_img):
+def test_image_counts(sc, n_img, one_sided):
     # compile-time image counts (0, 1, 2, 4, 8) and the run-time loop (others)
     p = synth.cylinder_load(700, seed=5)
-    acc, pot = run(sc, p, n_img)
+    acc, pot = run(sc, p, n_img, one_sided)
     a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, n_img)
     assert rel_err(acc, a_ref).max() <= TOL_ACC
     assert pot_err(pot, p_ref).max() <= TOL_POT
@@ -88,16 +98,21 @@ def test_image_counts(sc, n_img):
 
 def test_potential_off_leaves_acceleration_bitwise(sc):
     p = synth.cylinder_load(1500, seed=7)
-    acc1, _ = run(sc, p, 8)
-    acc2, pot2 = run(sc, p, 8, potential=False)
+    acc1, _ = run(sc, p, 8, True)
+    acc2, pot2 = run(sc, p, 8, True, potential=False)
     assert pot2 is None
     assert torch.equal(acc1, acc2)
+    # the pairwise sums meet in FP64 in a run-dependent order: equal to an
+    # FP32 rounding step
+    acc3, _ = run(sc, p, 8)
+    acc4, _ = run(sc, p, 8, potential=False)
+    assert torch.allclose(acc3, acc4, rtol=3e-7, atol=0.0)
 
 
 def test_target_subset_is_bitwise_the_full_result(sc):
     p = synth.cylinder_load(3000, seed=8)
     pos, m, e = to_dev(p)
-    acc, pot = sc.steps_cyl_forces(pos, m, e, p.L, 8)
+    acc, pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8)
     t = torch.tensor([0, 5, 2999, 5, 1234, 17, 256, 255], dtype=torch.int64, device=pos.device)
     acc2, pot2 = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t)
     torch.cuda.synchronize()
@@ -119,7 +134,8 @@ def test_plain_mode_parity_and_difference(sc):
     assert not torch.equal(acc_c, acc_p)
 
 
-def test_softened_coincident_and_clumped_pairs(sc):
+@pytest.mark.parametrize("one_sided", [False, True])
+def test_softened_coincident_and_clumped_pairs(sc, one_sided):
     # a tight clump inside the softening lengths, two coincident particles and
     # a particle exactly on another's axis position
     base = synth.cylinder_load(900, seed=9)
@@ -129,30 +145,32 @@ def test_softened_coincident_and_clumped_pairs(sc):
     pos[:, 200] = pos[:, 201]
     pos[2] = np.mod(pos[2], 1.0)
     p = synth.Particles(pos, base.mass, base.eps, base.L)
-    acc, pot = run(sc, p, 8)
+    acc, pot = run(sc, p, 8, one_sided)
     a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8)
     assert rel_err(acc, a_ref).max() <= TOL_ACC
     assert pot_err(pot, p_ref).max() <= TOL_POT
 
 
-def test_large_softening_softens_images_too(sc):
+@pytest.mark.parametrize("one_sided", [False, True])
+def test_large_softening_softens_images_too(sc, one_sided):
     # h_i + h_j > L/2: the images n != 0 fall inside the spline core
     p = synth.tiny_load(300, seed=4, box=0.5)
     eps = np.full(p.N, 0.3)
     q = synth.Particles(p.pos, p.mass, eps, p.L)
-    acc, pot = run(sc, q, 4)
+    acc, pot = run(sc, q, 4, one_sided)
     a_ref, p_ref = oracle.forces(q.pos, q.mass, q.eps, q.L, 4)
     assert rel_err(acc, a_ref).max() <= TOL_ACC
     assert pot_err(pot, p_ref).max() <= TOL_POT
 
 
-def test_unwrapped_positions_and_other_period(sc):
+@pytest.mark.parametrize("one_sided", [False, True])
+def test_unwrapped_positions_and_other_period(sc, one_sided):
     p = synth.tiny_load(600, seed=6, L=2.5, box=1.5)
     pos = p.pos.copy()
     pos[2, ::3] += 2.5 * 3
     pos[2, 1::3] -= 2.5 * 2
     q = synth.Particles(pos, p.mass, p.eps, 2.5)
-    acc, pot = run(sc, q, 8)
+    acc, pot = run(sc, q, 8, one_sided)
     a_ref, p_ref = oracle.forces(q.pos, q.mass, q.eps, q.L, 8)
     assert rel_err(acc, a_ref).max() <= TOL_ACC
     assert pot_err(pot, p_ref).max() <= TOL_POT
@@ -160,9 +178,13 @@ def test_unwrapped_positions_and_other_period(sc):
 
 def test_deterministic(sc):
     p = synth.cylinder_load(5000, seed=10)
-    a1, p1 = run(sc, p, 8)
-    a2, p2 = run(sc, p, 8)
+    a1, p1 = run(sc, p, 8, True)
+    a2, p2 = run(sc, p, 8, True)
     assert torch.equal(a1, a2) and torch.equal(p1, p2)
+    # pairwise: FP64 sums in a run-dependent order, equal to an FP32 rounding step
+    a3, p3 = run(sc, p, 8)
+    a4, p4 = run(sc, p, 8)
+    assert torch.allclose(a3, a4, rtol=3e-7, atol=0.0) and torch.allclose(p3, p4, rtol=3e-7, atol=0.0)
 
 
 def test_f64_reference_matches_oracle(sc):
@@ -176,9 +198,10 @@ def test_f64_reference_matches_oracle(sc):
     assert pot_err(pot, p_ref).max() <= 1e-12
 
 
-def test_config2_clustered_sampled(sc):
+@pytest.mark.parametrize("one_sided", [False, True])
+def test_config2_clustered_sampled(sc, one_sided):
     p = synth.clustered_load(262144, seed=0)
-    acc, pot = run(sc, p, 8)
+    acc, pot = run(sc, p, 8, one_sided)
     t = synth.target_sample(p.N, 384, seed=0)
     # include clump members (the last 83,904 particles are in clumps)
     t = np.unique(np.concatenate([t, np.arange(p.N - 64, p.N)]))
@@ -213,7 +236,7 @@ def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc):
     # is unchanged, so it equals bit for bit the same targets asked for by index
     p = synth.clustered_load(12000, n_clumps=8, clump_frac=0.02, seed=46)
     pos, m, e = (torch.from_numpy(x).cuda() for x in (p.pos, p.mass, p.eps))
-    full, fpot = sc.steps_cyl_forces(pos, m, e, p.L, 8)
+    full, fpot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8)
     tg = torch.from_numpy(synth.target_sample(p.N, 700, seed=47)).cuda()
     sub, spot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=tg)
     torch.cuda.synchronize()
@@ -226,7 +249,7 @@ def test_long_target_lists_in_spatial_order_are_bitwise_exact(sc):
     # and any order give, per list position, the full call's result bit for bit
     p = synth.clustered_load(12000, n_clumps=8, clump_frac=0.02, seed=50)
     pos, m, e = to_dev(p)
-    full, fpot = sc.steps_cyl_forces(pos, m, e, p.L, 8)
+    full, fpot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8)
     rng = np.random.default_rng(51)
     tg = torch.from_numpy(rng.integers(0, p.N, 6000)).cuda()
     sub, spot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=tg)
