@@ -317,8 +317,13 @@ int steps_cyl_table_info(const steps_cyl_table *table, int *n_delta, int *n_rho,
 
 /* Accelerations with the exact images |n| <= 1 (spline-softened) plus the
  * interpolated band (order 1 = CIC, 2 = TSC); out_pot, when non-NULL, gets
- * the |n| <= 1 potential.  Other arguments as steps_cyl_forces_ex
- * (compensated summation). */
+ * the |n| <= 1 potential.  The table's far-image term is odd in d along z
+ * and even in d across, so the tabulated pair is antisymmetric like the
+ * exact one.  targets NULL (every particle a target): each unordered pair is
+ * evaluated once and applied to both particles, with the arithmetic, run-to-
+ * run reproducibility and stream-ordered scratch of steps_cyl_forces.  An
+ * explicit target list: one thread per target with Kahan-compensated FP32
+ * sums, bitwise deterministic.  Other arguments as steps_cyl_forces_ex. */
 int steps_cyl_forces_table(const double *pos, const double *mass, const double *eps,
                            int64_t N, double L, const steps_cyl_table *table, int order,
                            const int64_t *targets, int64_t n_targets,

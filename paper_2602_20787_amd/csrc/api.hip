@@ -6,8 +6,6 @@ namespace steps {
 int launch_forces_exact(const double *pos, const double *mass, const double *eps, int64_t N,
                         double L, int n_img, const int64_t *targets, int64_t n_tgt, int mode,
                         float *out_acc, float *out_pot, hipStream_t stream);
-int launch_forces_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
-                           int n_img, float *out_acc, float *out_pot, hipStream_t stream);
 int launch_forces_f64(const double *pos, const double *mass, const double *eps, int64_t N,
                       double L, int n_img, const int64_t *targets, int64_t n_tgt, double *out_acc,
                       double *out_pot, hipStream_t stream);
@@ -45,7 +43,7 @@ STEPS_API int steps_cyl_forces(const double *pos, const double *mass, const doub
     if (rc) return rc;
     if ((rc = require_device())) return rc;
     clear_error();
-    return launch_forces_pairwise(pos, mass, eps, N, L, n_img, out_acc, out_pot, stream);
+    return launch_forces_pairwise(pos, mass, eps, N, L, n_img, nullptr, 0, out_acc, out_pot, stream);
 }
 
 STEPS_API int steps_cyl_forces_ex(const double *pos, const double *mass, const double *eps,
@@ -61,7 +59,7 @@ STEPS_API int steps_cyl_forces_ex(const double *pos, const double *mass, const d
     if ((rc = require_device())) return rc;
     clear_error();
     if (mode == STEPS_SUM_PAIRWISE)
-        return launch_forces_pairwise(pos, mass, eps, N, L, n_img, out_acc, out_pot, stream);
+        return launch_forces_pairwise(pos, mass, eps, N, L, n_img, nullptr, 0, out_acc, out_pot, stream);
     return launch_forces_exact(pos, mass, eps, N, L, n_img, targets, n_targets, mode, out_acc,
                                out_pot, stream);
 }

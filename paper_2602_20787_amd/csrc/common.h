@@ -36,6 +36,14 @@ int order_targets(const double *pos, int64_t N, double L, const int64_t *targets
 // target lists at least this long are walked in spatial order
 constexpr int64_t kOrderTargetsMin = 4096;
 
+// The pairwise path (forces_pairwise.hip) for all N particles: every
+// unordered pair once, exact images |n| <= n_img, or with a table (non-null)
+// images |n| <= 1 plus its far images (order 1 CIC, 2 TSC).  Arguments are
+// validated by the caller.
+int launch_forces_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
+                           int n_img, const steps_cyl_table *table, int order, float *out_acc, float *out_pot,
+                           hipStream_t stream);
+
 }  // namespace steps
 
 #define STEPS_CHECK_HIP(expr)                                          \

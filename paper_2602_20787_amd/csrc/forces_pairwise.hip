@@ -28,6 +28,7 @@
 #include "common.h"
 #include "pair_f64.h"
 #include "pair_fp32.h"
+#include "table_pair.h"
 
 namespace steps {
 
@@ -43,8 +44,29 @@ struct PairwiseArgs {
     double *acc;        // [4][N] sums in spatial order (x, y, z, potential)
     double L, invL, halfL, tie;  // tie: |d| within this of L/2 takes the check
     ImageConsts c;
+    TableView tv;       // far-image table (table paths only)
+    float invLf, invL2f;
     int N, G, P;        // particles, groups, workgroups per group
 };
+
+// Exact band 2 <= |n| <= n_far of one pair in one lane (delta = d/L signed,
+// r = rho/L; per unit G m / L^2): the rare fallback of band tables for
+// pairs beyond the table's rho range.
+__device__ __noinline__ void band_serial(float delta, float r, int n_far, float &fz, float &fr) {
+    const float r2 = r * r;
+    float sz = 0.f, sr = 0.f;
+    for (int q = n_far; q >= 2; --q) {
+        const float qf = (float)q;
+        const float up = delta - qf, um = delta + qf;
+        const float ip = __builtin_amdgcn_rsqf(__builtin_fmaf(up, up, r2));
+        const float im = __builtin_amdgcn_rsqf(__builtin_fmaf(um, um, r2));
+        const float ip3 = ip * ip * ip, im3 = im * im * im;
+        sz = __builtin_fmaf(-up, ip3, __builtin_fmaf(-um, im3, sz));
+        sr = __builtin_fmaf(-r, ip3 + im3, sr);
+    }
+    fz = sz;
+    fr = sr;
+}
 
 __global__ void stage_kernel(const double *pos, const double *mass, const double *eps, int N, double L,
                              const int *perm, SrcRec *rec, double *acc) {
@@ -88,7 +110,7 @@ struct Owned {
 // Pair terms are FP32; both sides are summed in FP64 (the records are in
 // spatial order, so a particle's near neighbours arrive together and an
 // FP32 partial would lose their cancellation).
-template <int NIMG, bool POT, bool REACT>
+template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT>
 __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned &o, const SrcRec *tile, int base,
                                           int cnt, float hmax, double (*acc)[4], double (*jpart)[kTile][4]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -103,7 +125,7 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned &o,
     for (int si = 0; si < cnt; ++si) {
         const SrcRec src = tile[si];
         double dx64[kR], dy64[kR];
-        float S[kR], Fz[kR], P[kR];
+        float S[kR], Fz[kR], P[kR], dr[kR];
         bool tie[kR];
         unsigned soft = 0;  // bit r: the pair (r, src) takes the FP64 spline
 #pragma unroll
@@ -112,6 +134,7 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned &o,
             dy64[r] = o.y[r] - src.y;
             const double d64 = min_image(o.z[r] - src.z, a.L, a.invL);
             const float dx = (float)dx64[r], dy = (float)dy64[r], d = (float)d64;
+            dr[r] = d;
             P[r] = 0.f;
             pair_fast<NIMG, POT>(dx, dy, d, a.c, S[r], Fz[r], P[r]);
             const float r2_0 = __builtin_fmaf(d, d, __builtin_fmaf(dx, dx, dy * dy));
@@ -152,6 +175,51 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned &o,
                     Fz[k] = gF;
                     P[k] = gP;
                 }
+        }
+        if (TORDER > 0) {
+            // far images from the table (Sect. 2.2, eq. S1R2EwaldCorrectionTable):
+            // R_z is odd in d and R_rho even, so the corrected pair keeps the
+            // symmetry of the exact one
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                const float dx = (float)dx64[r], dy = (float)dy64[r];
+                const float rho = __builtin_sqrtf(__builtin_fmaf(dx, dx, dy * dy));
+                const float rr = rho * a.invLf;
+                const float delta = __builtin_fabsf(dr[r]) * a.invLf;
+                const bool self = !REACT && base + si == o.t[r];
+                const bool inside = (rr <= a.tv.r_max) && !self;
+                float tz, tr;
+                lookup<(TORDER > 0 ? TORDER : 1)>(a.tv, delta, inside ? rr : 0.f, tz, tr);
+                float Rz = (dr[r] > 0.f) ? tz : ((dr[r] < 0.f) ? -tz : 0.f);
+                float Rr = tr;
+                if (!inside) {
+                    Rz = 0.f;
+                    Rr = 0.f;
+                    if (!self) {
+                        const float ds = dr[r] * a.invLf;
+                        if (COMPLETE) {
+                            // line-mass limit of the complete sum minus the images |n| <= 1
+                            const float r2 = rr * rr;
+                            float nz = 0.f, nr = 0.f;
+#pragma unroll
+                            for (int n = -1; n <= 1; ++n) {
+                                const float u = ds - (float)n;
+                                const float iq = __builtin_amdgcn_rsqf(__builtin_fmaf(u, u, r2));
+                                const float iq3 = iq * iq * iq;
+                                nz = __builtin_fmaf(-u, iq3, nz);
+                                nr = __builtin_fmaf(-rr, iq3, nr);
+                            }
+                            Rz = -nz;
+                            Rr = -2.f * __builtin_amdgcn_rcpf(rr) - nr;
+                        } else {
+                            band_serial(ds, rr, a.tv.n_far, Rz, Rr);
+                        }
+                    }
+                }
+                const float rinv = rho > 0.f ? __builtin_amdgcn_rcpf(rho) : 0.f;
+                S[r] = __builtin_fmaf(-Rr * a.invL2f, rinv, S[r]);
+                Fz[r] = __builtin_fmaf(-Rz, a.invL2f, Fz[r]);
+            }
         }
         const double ms = (double)src.m;
         double jx = 0.0, jy = 0.0, jz = 0.0, jp = 0.0;
@@ -197,7 +265,7 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned &o,
     }
 }
 
-template <int NIMG, bool POT>
+template <int NIMG, bool POT, int TORDER, bool COMPLETE>
 __global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseArgs a) {
     __shared__ SrcRec tile[kTile];
     __shared__ float wave_hmax[kThreads / 64];
@@ -254,10 +322,10 @@ __global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseAr
             for (int w = 1; w < kThreads / 64; ++w) hmax = fmaxf(hmax, wave_hmax[w]);
             const int cnt = gend - base < kTile ? gend - base : kTile;
             if (u == 0) {
-                tile_pass<NIMG, POT, false>(a, o, tile, base, cnt, hmax, acc, jpart);
+                tile_pass<NIMG, POT, TORDER, COMPLETE, false>(a, o, tile, base, cnt, hmax, acc, jpart);
                 __syncthreads();
             } else {
-                tile_pass<NIMG, POT, true>(a, o, tile, base, cnt, hmax, acc, jpart);
+                tile_pass<NIMG, POT, TORDER, COMPLETE, true>(a, o, tile, base, cnt, hmax, acc, jpart);
                 __syncthreads();
                 if (tid < cnt) {
                     // reaction on source base + tid, in the owned sums' sign convention
@@ -285,31 +353,41 @@ __global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseAr
     }
 }
 
-template <int NIMG, bool POT>
+template <int NIMG, bool POT, int TORDER, bool COMPLETE>
 hipError_t launch_t(const PairwiseArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL((forces_pairwise_kernel<NIMG, POT>), dim3(a.G * a.P), dim3(kThreads), 0, stream, a);
+    hipLaunchKernelGGL((forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE>), dim3(a.G * a.P), dim3(kThreads), 0,
+                       stream, a);
     return hipGetLastError();
 }
 
 template <bool POT>
 hipError_t launch_nimg(const PairwiseArgs &a, hipStream_t stream) {
     switch (a.c.n_img) {
-        case 0: return launch_t<0, POT>(a, stream);
-        case 1: return launch_t<1, POT>(a, stream);
-        case 2: return launch_t<2, POT>(a, stream);
-        case 4: return launch_t<4, POT>(a, stream);
-        case 8: return launch_t<8, POT>(a, stream);
-        default: return launch_t<-1, POT>(a, stream);
+        case 0: return launch_t<0, POT, 0, false>(a, stream);
+        case 1: return launch_t<1, POT, 0, false>(a, stream);
+        case 2: return launch_t<2, POT, 0, false>(a, stream);
+        case 4: return launch_t<4, POT, 0, false>(a, stream);
+        case 8: return launch_t<8, POT, 0, false>(a, stream);
+        default: return launch_t<-1, POT, 0, false>(a, stream);
     }
+}
+
+template <bool POT>
+hipError_t launch_table(const PairwiseArgs &a, int order, bool complete, hipStream_t stream) {
+    if (order == 1)
+        return complete ? launch_t<1, POT, 1, true>(a, stream) : launch_t<1, POT, 1, false>(a, stream);
+    return complete ? launch_t<1, POT, 2, true>(a, stream) : launch_t<1, POT, 2, false>(a, stream);
 }
 
 }  // namespace
 
-// Launches the pairwise exact-force path for all N particles; arguments
-// already validated.  Scratch (spatial order, records, FP64 sums) is
+// Launches the pairwise path for all N particles: exact images |n| <= n_img,
+// or (table non-null) images |n| <= 1 plus the table's far images with CIC
+// (order 1) or TSC (order 2) interpolation.  Arguments already validated.  Scratch (spatial order, records, FP64 sums) is
 // stream-ordered.
 int launch_forces_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
-                           int n_img, float *out_acc, float *out_pot, hipStream_t stream) {
+                           int n_img, const steps_cyl_table *table, int order, float *out_acc, float *out_pot,
+                           hipStream_t stream) {
     void *order_scratch = nullptr;
     const int *perm = nullptr;
     int rc = order_targets(pos, N, L, nullptr, N, stream, &order_scratch, &perm);
@@ -331,7 +409,10 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
     a.c.Lf = (float)L;
     a.c.L2f = (float)(L * L);
     a.c.m2Lf = (float)(-2.0 * L);
-    a.c.n_img = n_img;
+    a.c.n_img = table ? 1 : n_img;
+    a.invLf = (float)(1.0 / L);
+    a.invL2f = (float)(1.0 / (L * L));
+    if (table) a.tv = table_view(table);
     a.N = (int)N;
     a.G = (int)((N + kGroup - 1) / kGroup);
     // enough workgroups to fill the chip: about 2048, never more than the
@@ -342,7 +423,13 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
     hipLaunchKernelGGL(stage_kernel, dim3(nb), dim3(256), 0, stream, pos, mass, eps, (int)N, L, perm,
                        (SrcRec *)buf, a.acc);
     e = hipGetLastError();
-    if (e == hipSuccess) e = out_pot ? launch_nimg<true>(a, stream) : launch_nimg<false>(a, stream);
+    if (e == hipSuccess) {
+        if (table)
+            e = out_pot ? launch_table<true>(a, order, table->complete != 0, stream)
+                        : launch_table<false>(a, order, table->complete != 0, stream);
+        else
+            e = out_pot ? launch_nimg<true>(a, stream) : launch_nimg<false>(a, stream);
+    }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(finish_kernel, dim3(nb), dim3(256), 0, stream, a.acc, perm, (int)N, out_acc,
                            out_acc + N, out_acc + 2 * N, out_pot);

@@ -31,8 +31,6 @@
 
 namespace steps {
 
-int launch_forces_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
-                           int n_img, float *out_acc, float *out_pot, hipStream_t stream);
 int launch_forces_learned(const double *pos, const double *mass, const double *eps, int64_t N, double L,
                           const steps_cyl_mlp *net, const int64_t *targets, int64_t n_tgt, int mode,
                           float *out_acc, float *out_pot, hipStream_t stream);
@@ -425,7 +423,7 @@ STEPS_API int steps_cyl_kdk_step(double *pos, double *mom, const double *mass, c
         rc = steps_cyl_forces_table(pos, mass, eps, N, L, params->table, params->table_order, nullptr, N,
                                     acc_inout, nullptr, stream);
     else
-        rc = launch_forces_pairwise(pos, mass, eps, N, L, params->n_img, acc_inout, nullptr, stream);
+        rc = launch_forces_pairwise(pos, mass, eps, N, L, params->n_img, nullptr, 0, acc_inout, nullptr, stream);
     if (rc) return rc;
     hipLaunchKernelGGL(kick_kernel, grid, block, 0, stream, pos, mom, acc_inout, N, f[2], c, params->compensate);
     return hip_status(hipGetLastError(), "kick kernel");

@@ -401,6 +401,8 @@ STEPS_API int steps_cyl_forces_table(const double *pos, const double *mass, cons
     int rc = require_device();
     if (rc) return rc;
     clear_error();
+    // every particle a target: each unordered pair once
+    if (!targets) return launch_forces_pairwise(pos, mass, eps, N, L, 1, t, order, out_acc, out_pot, stream);
     TableArgs a;
     a.x = pos;
     a.y = pos + N;

@@ -106,7 +106,8 @@ def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc, order, 
     p = synth.cylinder_load(9000, seed=44)
     t = sc.CorrectionTable.ewald(24, 16, 4.0, 2.0, 5, 12) if complete else sc.CorrectionTable(24, 16, 5.0, 1024)
     pos, m, e = to_dev(p)
-    full, fpot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order)
+    every = torch.arange(p.N, dtype=torch.int64, device=pos.device)  # per-target path
+    full, fpot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order, targets=every)
     tg = torch.from_numpy(synth.target_sample(p.N, 500, seed=45)).cuda()
     sub, spot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order, targets=tg)
     torch.cuda.synchronize()
@@ -119,11 +120,42 @@ def test_long_target_lists_in_spatial_order_are_bitwise_exact(sc):
     p = synth.cylinder_load(9000, seed=53)
     t = sc.CorrectionTable(24, 16, 5.0, 1024)
     pos, m, e = to_dev(p)
-    full, fpot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=1)
+    every = torch.arange(p.N, dtype=torch.int64, device=pos.device)  # per-target path
+    full, fpot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=1, targets=every)
     rng = np.random.default_rng(54)
     tg = torch.from_numpy(rng.integers(0, p.N, 5000)).cuda()
     sub, spot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=1, targets=tg)
     torch.cuda.synchronize()
     assert torch.equal(full[:, tg], sub)
     assert torch.equal(fpot[tg], spot)
+    t.close()
+
+
+@pytest.mark.parametrize("order,complete,rho_max", [(1, False, 6.4), (2, False, 5.0), (1, True, 4.0),
+                                                    (2, True, 6.4)])
+def test_pairwise_table_path_matches_per_target_path_and_oracle(sc, order, complete, rho_max):
+    # targets NULL evaluates every unordered pair once; rho_max below the
+    # load's largest separation sends some pairs to the band (serial in one
+    # lane) or to the line-mass limit (complete tables)
+    p = synth.cylinder_load(7000, seed=60)
+    t = (sc.CorrectionTable.ewald(24, 16, rho_max, 2.0, 5, 12) if complete
+         else sc.CorrectionTable(24, 16, rho_max, 1024))
+    pos, m, e = to_dev(p)
+    print(f"[case] pairwise table order={order} complete={complete} rho_max={rho_max}", flush=True)
+    full, fpot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order)
+    every = torch.arange(p.N, dtype=torch.int64, device=pos.device)
+    one, opot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order, targets=every)
+    torch.cuda.synchronize()
+    # the two paths sum the same FP32 pair terms in FP64 and in compensated
+    # FP32: they differ by the per-target path's rounding (2.6e-6 seen)
+    assert rel(full, one).max() <= 1e-5
+    assert (torch.abs(fpot.double() - opot.double()) / torch.abs(opot.double())).max().item() <= 2e-6
+    tg = synth.target_sample(p.N, 64, seed=61)
+    tab = (ot.Table.ewald(24, 16, rho_max, 2.0, 5, 12) if complete else ot.Table(24, 16, rho_max))
+    ref = ot.forces_table(p.pos, p.mass, p.eps, p.L, tab, order, targets=tg)
+    assert rel(full[:, torch.from_numpy(tg).cuda()], ref).max() <= 2e-5
+    # the pairs are applied with opposite signs: momentum to rounding
+    f = full.double().cpu().numpy()
+    mom = np.abs((p.mass[None, :] * f).sum(axis=1)) / (p.mass[None, :] * np.abs(f)).sum(axis=1)
+    assert mom.max() <= 1e-6
     t.close()
