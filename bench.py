@@ -37,12 +37,12 @@ PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak (packed FMA
 PEAK_FP32_UNPACKED = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 
 
-# HBM bytes per launch of forces_pairwise_kernel<8,true> at N = 2^20 from the
+# HBM bytes per launch of forces_pairwise_kernel<8,true,0,false> at N = 2^20 from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter
 # reads for a 256 MiB copy (profiles/forces_pairwise_N1M_nimg8_counters.md).
 # Valid only for the kernel sources they were measured on (hash below).
-TRAFFIC_EXACT_N1M = {"bytes": 2.6366e+10, "fetch_scale": 1.99972, "write_scale": 1.0,
-                     "sources_sha256_16": "d1b46e6f4551d6fb"}
+TRAFFIC_EXACT_N1M = {"bytes": 2.6346e+10, "fetch_scale": 1.99967, "write_scale": 1.0,
+                     "sources_sha256_16": "b5a59d60e98c7abf"}
 TRAFFIC_SOURCES = ["forces_pairwise.hip", "pair_fp32.h", "pair_f64.h", "target_order.hip"]
 
 
@@ -165,7 +165,7 @@ def exact_leg(args, dev):
             "flops_per_evaluation": flops_per_pair(n_img) + REACTION_FLOPS,
             "evaluations": evals,
             "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_UNPACKED, 4),
-            "kernel": "forces_pairwise_kernel<8,true>",
+            "kernel": "forces_pairwise_kernel<8,true,0,false>",
         },
         "one_sided": {
             "ms": round(ms1, 3), "G_pairs_per_s": round(pairs / (ms1 * 1e-3) / 1e9, 3),
