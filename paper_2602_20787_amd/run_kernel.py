@@ -16,7 +16,9 @@ times, timed with HIP events on the stream it runs on.  Paths:
 * ``tree``     steps_cyl_tree_forces with the complete 144 x 128 table (CIC)
 
 --targets K takes the first K particles as targets (all sources are always
-used); the tree path always computes every particle.  The potential is
+used; --explicit-targets passes them as a list even when K = N, which selects
+the per-target kernels of the table path); the tree path always computes
+every particle.  The potential is
 skipped except for ``exact`` with --potential.  Prints one JSON line: the
 path, sizes, milliseconds per call and pair interactions per second (for
 the direct paths).
@@ -41,6 +43,8 @@ def main(argv=None):
     ap.add_argument("--path", choices=["exact", "learned", "table", "tree"], required=True)
     ap.add_argument("--N", type=int, default=1 << 20)
     ap.add_argument("--targets", type=int, default=0, help="first K particles as targets (0: all)")
+    ap.add_argument("--explicit-targets", action="store_true",
+                    help="pass the targets as a list even when all are taken (per-target kernels)")
     ap.add_argument("--n-img", type=int, default=8)
     ap.add_argument("--potential", action="store_true")
     ap.add_argument("--pairwise", action="store_true")
@@ -64,7 +68,7 @@ def main(argv=None):
     e = torch.from_numpy(p.eps).to(dev)
     N = args.N
     K = N if args.targets <= 0 or args.path == "tree" else min(args.targets, N)
-    tg = None if K == N else torch.arange(K, dtype=torch.int64, device=dev)
+    tg = None if (K == N and not args.explicit_targets) else torch.arange(K, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream(dev)
     out = torch.empty((3, K), dtype=torch.float32, device=dev)
 

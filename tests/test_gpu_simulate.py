@@ -41,6 +41,7 @@ def test_driver_runs_each_mode(sim, capsys, mode, med, err, pz):
 @pytest.mark.parametrize("argv", [["--path", "exact", "--targets", "1000", "--potential"],
                                   ["--path", "learned", "--targets", "4096"],
                                   ["--path", "table", "--order", "2"],
+                                  ["--path", "table", "--order", "1", "--explicit-targets"],
                                   ["--path", "tree", "--quadrupole"]])
 def test_profiling_driver_runs_each_path(capsys, argv):
     if not torch.cuda.is_available():
