@@ -1,11 +1,14 @@
-// Exact image-sum forces of all N particles with every unordered pair
-// evaluated once (Sect. 2.1, eqs. ComovingEquationsOfMotion and
-// ForceCylindrical).  The pair term is odd in the separation: the image set
-// {d - nL, |n| <= n_img} of the pair (j, i) is the negated set of (i, j), so
-// S and P are shared and F_z, dx, dy change sign.  The exception is an axial
+// Forces of all N particles with every unordered pair evaluated once
+// (Sect. 2.1, eqs. ComovingEquationsOfMotion and ForceCylindrical; with a
+// table, the far images of Sect. 2.2, eq. S1R2EwaldCorrectionTable).  The
+// pair term is odd in the separation: the image set {d - nL, |n| <= n_img}
+// of the pair (j, i) is the negated set of (i, j), so S and P are shared and
+// F_z, dx, dy change sign; the table's far-image term is odd in d along z
+// and even across, so the same holds with it.  The exception is an axial
 // separation of L/2 (up to rounding), where both particles may take a
 // minimum image of the same sign; F_z then keeps its sign.  Evaluating each
-// pair once halves the arithmetic of the one-sided kernel (forces_exact.hip).
+// pair once halves the arithmetic of the per-target kernels
+// (forces_exact.hip, table.hip).
 //
 // Layout.  The particles are put in spatial (Morton) order and staged as
 // 32-byte records {x, y, z wrapped, m, h}; groups of 1024 consecutive
@@ -18,10 +21,10 @@
 // Workgroup.  256 threads own the 1024 particles of their group, 4 each, in
 // registers.  Partner records come through LDS in tiles of 256.  For each
 // source a thread adds the FP32 pair term to its 4 own FP64 sums and the
-// reaction m_i (...) over its 4 particles into one FP64 register set; the
-// wave reduces those 4 values over its 64 lanes (a
-// reduce-scatter that leaves one component per 16 lanes) and writes them to
-// LDS; after the tile the 4 waves' values are added and the source's
+// reaction over its 4 particles into one FP64 register set; the wave
+// reduces those 4 values over its 64 lanes (a reduce-scatter that leaves
+// one component per 16 lanes) and writes them to LDS; after the tile the 4
+// waves' values are added and the source's
 // reaction goes to FP64 device accumulators with atomic adds.  The owned
 // particles' sums join the same accumulators at the end, and a last pass
 // converts them to FP32 outputs at the particles' own positions.
