@@ -46,6 +46,7 @@ struct PairwiseArgs {
     const SrcRec *rec;  // [N] records in spatial order
     double *acc;        // [4][N] sums in spatial order (x, y, z, potential)
     double L, invL, halfL, tie;  // tie: |d| within this of L/2 takes the check
+    float tie32;                 // FP32 screen for it: 0.5 L (1 - 1e-6), below every such |d|
     ImageConsts c;
     TableView tv;       // far-image table (table paths only)
     float invLf, invL2f;
@@ -143,7 +144,7 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned &o,
             const float r2_0 = __builtin_fmaf(d, d, __builtin_fmaf(dx, dx, dy * dy));
             const float hij = o.h[r] + src.h;
             if ((wide[r] || r2_0 < thr2[r]) && (r2_0 < hij * hij || hij > (float)a.halfL)) soft |= 1u << r;
-            tie[r] = REACT && __builtin_fabs(__builtin_fabs(d64) - a.halfL) <= a.tie;
+            tie[r] = REACT && __builtin_fabsf(d) >= a.tie32;
         }
         while (soft) {
             // rare and divergent: one pair per lane and pass, operands picked
@@ -240,8 +241,10 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned &o,
                 double fz = Fz64;
                 if (tie[r]) {
                     const double d64 = min_image(o.z[r] - src.z, a.L, a.invL);
-                    const double dji = min_image(src.z - o.z[r], a.L, a.invL);
-                    if ((dji < 0.0) == (d64 < 0.0)) fz = -Fz64;
+                    if (__builtin_fabs(__builtin_fabs(d64) - a.halfL) <= a.tie) {
+                        const double dji = min_image(src.z - o.z[r], a.L, a.invL);
+                        if ((dji < 0.0) == (d64 < 0.0)) fz = -Fz64;
+                    }
                 }
                 const double miS = o.m[r] * S64;
                 jx = __builtin_fma(miS, dx64[r], jx);
@@ -409,6 +412,7 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
     a.invL = 1.0 / L;
     a.halfL = 0.5 * L;
     a.tie = 1e-12 * L;
+    a.tie32 = (float)(0.5 * L * (1.0 - 1e-6));
     a.c.Lf = (float)L;
     a.c.L2f = (float)(L * L);
     a.c.m2Lf = (float)(-2.0 * L);
