@@ -105,7 +105,7 @@ __global__ void finish_kernel(const double *acc, const int *perm, int N, float *
 struct Owned {
     double x[kR], y[kR], z[kR];
     float h[kR], m[kR];
-    int t[kR];  // record index, or >= N for an empty slot
+    int t[kR];  // record index, or N for an empty slot
 };
 
 // The sources of one LDS tile against the thread's particles.  REACT: the
@@ -282,7 +282,8 @@ __global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseAr
     Owned o;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-        const int t = g * kGroup + r * kThreads + tid;
+        const int64_t t64 = (int64_t)g * kGroup + r * kThreads + tid;
+        const int t = t64 < a.N ? (int)t64 : a.N;  // a.N marks an empty slot
         o.t[r] = t;
         if (t < a.N) {
             const SrcRec rr = a.rec[t];
@@ -312,12 +313,13 @@ __global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseAr
     const int u0 = (int)((int64_t)q * U / a.P), u1 = (int)((int64_t)(q + 1) * U / a.P);
     for (int u = u0; u < u1; ++u) {
         const int h = (g + u) % a.G;
-        const int gbase = h * kGroup, gend = min(gbase + kGroup, a.N);
-        for (int base = gbase; base < gend; base += kTile) {
-            const int j = base + tid;
+        // index arithmetic that stays below N (no int overflow near 2^31)
+        const int gbase = h * kGroup, gend = gbase + min(kGroup, a.N - gbase);
+        for (int base = gbase, cnt = 0; base < gend; base += cnt) {
+            cnt = min(kTile, gend - base);
             float hj = 0.f;
-            if (j < gend) {
-                const SrcRec rr = a.rec[j];
+            if (tid < cnt) {
+                const SrcRec rr = a.rec[base + tid];
                 hj = rr.h;
                 tile[tid] = rr;
             }
@@ -326,7 +328,6 @@ __global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseAr
             __syncthreads();
             float hmax = wave_hmax[0];
             for (int w = 1; w < kThreads / 64; ++w) hmax = fmaxf(hmax, wave_hmax[w]);
-            const int cnt = gend - base < kTile ? gend - base : kTile;
             if (u == 0) {
                 tile_pass<NIMG, POT, TORDER, COMPLETE, false>(a, o, tile, base, cnt, hmax, acc, jpart);
                 __syncthreads();
