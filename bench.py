@@ -277,6 +277,16 @@ def learned_leg(args, dev):
     ms_t = {o: run_table(o) for o in (1, 2)}
     ms_l = run("learned")
     ms_x = run("exact")
+    # the learned correction over all particles at once: each unordered pair once
+    acc_pw = torch.empty((3, N), dtype=torch.float32, device=dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sc.steps_cyl_forces_learned(pos, m, e, p.L, net, out_acc=acc_pw, potential=False, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_lp = e0.elapsed_time(e1)
+    print(f"[bench] learned pairwise N={N} done ({ms_lp / 1e3:.1f} s)", file=sys.stderr, flush=True)
     t = torch.from_numpy(synth.target_sample(N, 1024, seed=7)).to(dev)
     ref, _ = sc.steps_cyl_forces_f64(pos, m, e, p.L, 1024, targets=t, potential=False)
     a8, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t, potential=False)
@@ -289,6 +299,7 @@ def learned_leg(args, dev):
         return float(f"{v.max():.3e}"), float(f"{np.median(v):.3e}")
 
     el, ex, e8 = err(acc_l[:, t]), err(acc_x[:, t]), err(a8)
+    elp = err(acc_pw[:, t])
     et = {o: err(acc_t[o][:, t]) for o in (1, 2)}
     pairs = float(N) * N
     net.close()
@@ -301,6 +312,11 @@ def learned_leg(args, dev):
         "learned_G_pairs_per_s": round(pairs / (ms_l * 1e-3) / 1e9, 3),
         "exact1024_G_pairs_per_s": round(pairs / (ms_x * 1e-3) / 1e9, 3),
         "speedup_learned_vs_exact1024": round(ms_x / ms_l, 2),
+        "learned_pairwise": {
+            "ms": round(ms_lp, 1), "G_pairs_per_s": round(pairs / (ms_lp * 1e-3) / 1e9, 3),
+            "speedup_vs_per_target_learned": round(ms_l / ms_lp, 2),
+            "max_rel_err": elp[0], "median_rel_err": elp[1],
+        },
         "err_vs_f64_exact1024_targets": 1024,
         "learned_max_rel_err": el[0], "learned_median_rel_err": el[1],
         "exact1024_fp32_max_rel_err": ex[0], "exact8_max_rel_err": e8[0],

@@ -244,14 +244,20 @@ int steps_cyl_mlp_load(const char *path, steps_cyl_mlp **out);
  * |n| <= 1 only (the network has no potential output).  Arguments as
  * steps_cyl_forces; `net` is a handle from steps_cyl_mlp_create/_load.
  * Softening of the replaced images is not modelled (they lie at least 1.5 L
- * away; h_i + h_j below that is assumed).
+ * away; h_i + h_j below that is assumed).  The learned pair term is odd in
+ * the separation (R_z odd in d, R_rho even), so, as in steps_cyl_forces,
+ * every unordered pair is evaluated once and applied to both particles, with
+ * FP64 sums, run-to-run agreement to one FP32 rounding step and
+ * stream-ordered scratch of about 80 bytes per particle.
  */
 int steps_cyl_forces_learned(const double *pos, const double *mass, const double *eps,
                              int64_t N, double L, const steps_cyl_mlp *net,
                              float *out_acc, float *out_pot, hipStream_t stream);
 
 /* As steps_cyl_forces_learned for a target subset and summation mode
- * (arguments as steps_cyl_forces_ex). */
+ * (arguments as steps_cyl_forces_ex): per target (STEPS_SUM_COMPENSATED,
+ * STEPS_SUM_PLAIN; bitwise deterministic) or, with targets NULL,
+ * STEPS_SUM_PAIRWISE (the path of steps_cyl_forces_learned). */
 int steps_cyl_forces_learned_ex(const double *pos, const double *mass, const double *eps,
                                 int64_t N, double L, const steps_cyl_mlp *net,
                                 const int64_t *targets, int64_t n_targets, int mode,

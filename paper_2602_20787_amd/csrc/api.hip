@@ -84,8 +84,7 @@ STEPS_API int steps_cyl_forces_learned(const double *pos, const double *mass, co
     if (!net) return fail(STEPS_EINVAL, "net must be non-null");
     if ((rc = require_device())) return rc;
     clear_error();
-    return launch_forces_learned(pos, mass, eps, N, L, net, nullptr, N, STEPS_SUM_COMPENSATED, out_acc,
-                                 out_pot, stream);
+    return launch_forces_learned_pairwise(pos, mass, eps, N, L, net, out_acc, out_pot, stream);
 }
 
 STEPS_API int steps_cyl_forces_learned_ex(const double *pos, const double *mass, const double *eps,
@@ -95,10 +94,14 @@ STEPS_API int steps_cyl_forces_learned_ex(const double *pos, const double *mass,
     int rc = check_common(pos, mass, eps, N, L, 1, targets, n_targets, out_acc);
     if (rc) return rc;
     if (!net) return fail(STEPS_EINVAL, "net must be non-null");
-    if (mode != STEPS_SUM_COMPENSATED && mode != STEPS_SUM_PLAIN)
+    if (mode != STEPS_SUM_COMPENSATED && mode != STEPS_SUM_PLAIN && mode != STEPS_SUM_PAIRWISE)
         return fail(STEPS_EINVAL, "mode=%d is not a summation mode", mode);
+    if (mode == STEPS_SUM_PAIRWISE && targets)
+        return fail(STEPS_EINVAL, "STEPS_SUM_PAIRWISE needs every particle as a target (targets NULL)");
     if ((rc = require_device())) return rc;
     clear_error();
+    if (mode == STEPS_SUM_PAIRWISE)
+        return launch_forces_learned_pairwise(pos, mass, eps, N, L, net, out_acc, out_pot, stream);
     return launch_forces_learned(pos, mass, eps, N, L, net, targets, n_targets, mode, out_acc, out_pot,
                                  stream);
 }

@@ -44,6 +44,11 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
                            int n_img, const steps_cyl_table *table, int order, float *out_acc, float *out_pot,
                            hipStream_t stream);
 
+// The learned correction's pairwise path for all N particles
+// (forces_learned.hip); arguments validated by the caller.
+int launch_forces_learned_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
+                                   const steps_cyl_mlp *net, float *out_acc, float *out_pot, hipStream_t stream);
+
 }  // namespace steps
 
 #define STEPS_CHECK_HIP(expr)                                          \

@@ -31,9 +31,6 @@
 
 namespace steps {
 
-int launch_forces_learned(const double *pos, const double *mass, const double *eps, int64_t N, double L,
-                          const steps_cyl_mlp *net, const int64_t *targets, int64_t n_tgt, int mode,
-                          float *out_acc, float *out_pot, hipStream_t stream);
 
 namespace {
 
@@ -413,8 +410,7 @@ STEPS_API int steps_cyl_kdk_step(double *pos, double *mom, const double *mass, c
     hipLaunchKernelGGL(drift_kernel, grid, block, 0, stream, pos, mom, N, f[1], L);
     STEPS_CHECK_HIP(hipGetLastError());
     if (params->net)
-        rc = launch_forces_learned(pos, mass, eps, N, L, params->net, nullptr, N, STEPS_SUM_COMPENSATED,
-                                   acc_inout, nullptr, stream);
+        rc = launch_forces_learned_pairwise(pos, mass, eps, N, L, params->net, acc_inout, nullptr, stream);
     else if (params->tree)
         rc = steps_cyl_tree_forces(params->tree, pos, mass, eps, N, L, params->R_cyl, params->table,
                                    params->table_order, params->theta, params->tree_shift, params->tree_angle,

@@ -11,6 +11,7 @@ times, timed with HIP events on the stream it runs on.  Paths:
 * ``exact``    steps_cyl_forces_ex with images |n| <= --n-img (--pairwise:
                every unordered pair once, STEPS_SUM_PAIRWISE; all targets)
 * ``learned``  steps_cyl_forces_learned_ex with the shipped network
+               (--pairwise: every unordered pair once; all targets)
 * ``table``    steps_cyl_forces_table with the 144 x 128 band table
                2 <= |n| <= 1024 (CIC or TSC, --order)
 * ``tree``     steps_cyl_tree_forces with the complete 144 x 128 table (CIC)
@@ -81,8 +82,10 @@ def main(argv=None):
     elif args.path == "learned":
         net = sc.Mlp.load(NET)
 
+        lmode = sc.STEPS_SUM_PAIRWISE if args.pairwise else sc.STEPS_SUM_COMPENSATED
+
         def call():
-            sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=tg, out_acc=out,
+            sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=tg, mode=lmode, out_acc=out,
                                            potential=False, stream=stream)
     elif args.path == "table":
         table = sc.CorrectionTable(128, 144, 6.4, 1024)
@@ -123,6 +126,8 @@ def main(argv=None):
         row["order"] = args.order
     if args.path == "exact":
         row.update({"n_img": args.n_img, "pairwise": args.pairwise, "potential": args.potential})
+    if args.path == "learned":
+        row["pairwise"] = args.pairwise
     print(json.dumps(row), flush=True)
 
 

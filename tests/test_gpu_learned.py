@@ -83,16 +83,41 @@ def test_learned_matches_oracle(sc, net):
 def test_learned_momentum_and_subset(sc, net):
     p = synth.cylinder_load(3000, seed=32)
     pos, m, e = to_dev(p)
-    acc, pot = sc.steps_cyl_forces_learned(pos, m, e, p.L, net)
+    acc, pot = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net)  # per target, all targets
     tt = torch.tensor([0, 2999, 77, 77, 1500], dtype=torch.int64, device=pos.device)
     acc2, pot2 = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=tt)
     torch.cuda.synchronize()
     assert torch.equal(acc2, acc[:, tt]) and torch.equal(pot2, pot[tt])
-    a = acc.double().cpu().numpy()
-    mom = np.abs((p.mass[None, :] * a).sum(axis=1))
-    scale = np.sum(p.mass * np.linalg.norm(a, axis=0))
-    print(f"|sum m a| / sum m|a| = {mom.max() / scale:.2e}")
-    assert mom.max() <= 1e-5 * scale
+    for a_t in (acc, sc.steps_cyl_forces_learned(pos, m, e, p.L, net)[0]):
+        a = a_t.double().cpu().numpy()
+        mom = np.abs((p.mass[None, :] * a).sum(axis=1))
+        scale = np.sum(p.mass * np.linalg.norm(a, axis=0))
+        print(f"|sum m a| / sum m|a| = {mom.max() / scale:.2e}")
+        assert mom.max() <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("N", [2, 129, 1000, 5000])
+def test_pairwise_learned_matches_per_target_and_oracle(sc, net, N):
+    # steps_cyl_forces_learned evaluates every unordered pair once (groups of
+    # 128: one group, ragged tails, odd and even group counts); the per-target
+    # kernel and the oracle of the learned scheme are the references
+    p = load_with_axis_line(N, seed=70 + N) if N >= 20 else synth.cylinder_load(N, seed=70)
+    pos, m, e = to_dev(p)
+    print(f"[case] pairwise learned N={N}", flush=True)
+    full, fpot = sc.steps_cyl_forces_learned(pos, m, e, p.L, net)
+    one, opot = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net)
+    torch.cuda.synchronize()
+    f = full.double().cpu().numpy()
+    assert rel_err(full, one.double().cpu().numpy()).max() <= 1e-5
+    assert (torch.abs(fpot.double() - opot.double()) / torch.abs(opot.double())).max().item() <= 1e-5
+    t = np.arange(N) if N <= 200 else np.unique(np.concatenate([np.arange(16), synth.target_sample(N, 60, seed=3)]))
+    ref = om.forces_learned(p.pos, p.mass, p.eps, p.L, net.params().astype(np.float64), targets=t)
+    assert rel_err(full[:, torch.from_numpy(t).cuda()], ref).max() <= TOL
+    # momentum: cross-group pairs cancel to rounding; pairs inside a group are
+    # evaluated from both ends, like the per-target kernel (the exact band of
+    # off-domain pairs sums its images in a sign-dependent order)
+    mom = np.abs((p.mass[None, :] * f).sum(axis=1)) / (p.mass[None, :] * np.abs(f)).sum(axis=1)
+    assert mom.max() <= 1e-5
 
 
 def test_learned_ragged_and_plain(sc, net):
@@ -110,7 +135,7 @@ def test_learned_ragged_and_plain(sc, net):
 def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc, net):
     p = synth.cylinder_load(9000, seed=48)
     pos, m, e = (torch.from_numpy(x).cuda() for x in (p.pos, p.mass, p.eps))
-    full, fpot = sc.steps_cyl_forces_learned(pos, m, e, p.L, net)
+    full, fpot = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net)  # per target, all targets
     tg = torch.from_numpy(synth.target_sample(p.N, 400, seed=49)).cuda()
     sub, spot = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=tg)
     torch.cuda.synchronize()
@@ -121,7 +146,7 @@ def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc, net):
 def test_long_target_lists_in_spatial_order_are_bitwise_exact(sc, net):
     p = synth.cylinder_load(9000, seed=55)
     pos, m, e = (torch.from_numpy(x).cuda() for x in (p.pos, p.mass, p.eps))
-    full, fpot = sc.steps_cyl_forces_learned(pos, m, e, p.L, net)
+    full, fpot = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net)  # per target, all targets
     rng = np.random.default_rng(56)
     tg = torch.from_numpy(rng.integers(0, p.N, 5000)).cuda()
     sub, spot = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=tg)
