@@ -42,7 +42,7 @@ PEAK_FP32_UNPACKED = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 # reads for a 256 MiB copy (profiles/forces_pairwise_N1M_nimg8_counters.md).
 # Valid only for the kernel sources they were measured on (hash below).
 TRAFFIC_EXACT_N1M = {"bytes": 2.5823e+10, "fetch_scale": 1.99969, "write_scale": 1.0,
-                     "sources_sha256_16": "937bce8c2a04a729"}
+                     "sources_sha256_16": "7b845ea30863bb94"}
 TRAFFIC_SOURCES = ["forces_pairwise.hip", "pair_fp32.h", "pair_f64.h", "target_order.hip"]
 
 

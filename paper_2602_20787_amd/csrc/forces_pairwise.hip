@@ -12,16 +12,16 @@
 //
 // Layout.  The particles are put in spatial (Morton) order and staged as
 // 32-byte records {x, y, z wrapped, m, h}; groups of 1024 consecutive
-// records are the unit of work.  Group g pairs with itself (one-sided, all
+// records (512 with a table) are the unit of work.  Group g pairs with itself (one-sided, all
 // ordered pairs, no reaction) and with the next K(g) groups modulo G, where
 // K = (G-1)/2 for odd G and G/2 - 1, plus one for the first half of the
 // groups, for even G; every unordered pair of groups then meets exactly
 // once.  The P workgroups of group g split its list of partner groups.
 //
-// Workgroup.  256 threads own the 1024 particles of their group, 4 each, in
-// registers.  Partner records come through LDS in tiles of 256.  For each
-// source a thread adds the FP32 pair term to its 4 own FP64 sums and the
-// reaction over its 4 particles into one FP64 register set; the wave
+// Workgroup.  256 threads own the particles of their group, 4 each (2 with a
+// table), in registers.  Partner records come through LDS in tiles of 256.  For each
+// source a thread adds the FP32 pair term to its own FP64 sums and the
+// reaction over its particles into one FP64 register set; the wave
 // reduces those 4 values over its 64 lanes (a reduce-scatter that leaves
 // one component per 16 lanes) and writes them to LDS; after the tile the 4
 // waves' values are added and the source's
@@ -38,8 +38,10 @@ namespace steps {
 namespace {
 
 constexpr int kThreads = 256;           // 4 waves
-constexpr int kR = 4;                   // particles per thread
-constexpr int kGroup = kThreads * kR;   // particles per group
+// particles per thread: 4 for the exact pair (fewer reactions to reduce and
+// add per pair); 2 with a table, whose gathers want the occupancy that the
+// smaller register set gives
+constexpr int particles_per_thread(int torder) { return torder > 0 ? 2 : 4; }
 constexpr int kTile = 256;              // sources per LDS tile
 
 struct PairwiseArgs {
@@ -102,6 +104,7 @@ __global__ void finish_kernel(const double *acc, const int *perm, int N, float *
     if (pot) pot[p] = (float)(-acc[3 * (int64_t)N + k]);
 }
 
+template <int kR>
 struct Owned {
     double x[kR], y[kR], z[kR];
     float h[kR], m[kR];
@@ -114,8 +117,8 @@ struct Owned {
 // Pair terms are FP32; both sides are summed in FP64 (the records are in
 // spatial order, so a particle's near neighbours arrive together and an
 // FP32 partial would lose their cancellation).
-template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT>
-__device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned &o, const SrcRec *tile, int base,
+template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT, int kR = particles_per_thread(TORDER)>
+__device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned<kR> &o, const SrcRec *tile, int base,
                                           int cnt, float hmax, double (*acc)[4], double (*jpart)[kTile][4]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float thr2[kR];
@@ -273,13 +276,15 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned &o,
 
 template <int NIMG, bool POT, int TORDER, bool COMPLETE>
 __global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseArgs a) {
+    constexpr int kR = particles_per_thread(TORDER);
+    constexpr int kGroup = kThreads * kR;  // particles per group
     __shared__ SrcRec tile[kTile];
     __shared__ float wave_hmax[kThreads / 64];
     __shared__ double jpart[kThreads / 64][kTile][4];
     const int tid = threadIdx.x;
     const int g = blockIdx.x / a.P, q = blockIdx.x % a.P;
 
-    Owned o;
+    Owned<kR> o;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int64_t t64 = (int64_t)g * kGroup + r * kThreads + tid;
@@ -422,7 +427,8 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
     a.invL2f = (float)(1.0 / (L * L));
     if (table) a.tv = table_view(table);
     a.N = (int)N;
-    a.G = (int)((N + kGroup - 1) / kGroup);
+    const int group = kThreads * particles_per_thread(table ? 1 : 0);
+    a.G = (int)((N + group - 1) / group);
     // enough workgroups to fill the chip: about 2048, never more than the
     // units of a group's list
     const int units = a.G / 2 + 1;
