@@ -66,6 +66,11 @@ typedef enum {
 /* Largest image count accepted by the force entry points. */
 #define STEPS_MAX_NIMG 4096
 
+/* Largest particle count (and target-list length) accepted by every entry
+ * point: 2^29, so that the kernels' 32-bit offsets into the SoA arrays
+ * (component c of particle i at c*N + i, c <= 3) never overflow. */
+#define STEPS_MAX_N (1LL << 29)
+
 /* Summation modes of steps_cyl_forces_ex. */
 #define STEPS_SUM_COMPENSATED 0   /* FP32 pairs, Kahan-compensated per-target sums */
 #define STEPS_SUM_PLAIN       1   /* FP32 pairs, plain FP32 per-target sums        */
@@ -79,7 +84,7 @@ typedef enum {
  *   pos      device, 3N doubles, SoA (x | y | z)
  *   mass     device, N doubles, >= 0
  *   eps      device, N doubles, > 0 (softening length h_i)
- *   N        number of particles, 1 <= N <= 2^31 - 1
+ *   N        number of particles, 1 <= N <= STEPS_MAX_N
  *   L        period along z, finite and > 0
  *   n_img    images n = -n_img..n_img per pair, 0 <= n_img <= STEPS_MAX_NIMG
  *   out_acc  device, 3N floats, SoA (a_x | a_y | a_z), written
@@ -110,7 +115,7 @@ int steps_cyl_forces(const double *pos, const double *mass, const double *eps,
  *
  *   targets    device, n_targets int64 indices in [0, N) (repeats allowed),
  *              or NULL for every particle (then n_targets must equal N)
- *   n_targets  number of targets, >= 1
+ *   n_targets  number of targets, 1 <= n_targets <= STEPS_MAX_N
  *   mode       STEPS_SUM_COMPENSATED (one thread per target, FP32 pair
  *              terms, Kahan-compensated FP32 sums, bitwise deterministic),
  *              STEPS_SUM_PLAIN (the same with plain FP32 sums), or

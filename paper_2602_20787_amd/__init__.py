@@ -15,7 +15,7 @@ __all__ = [
     "StepsError", "lib", "library_path",
     "steps_cyl_forces", "steps_cyl_forces_ex", "steps_cyl_forces_f64",
     "steps_cyl_last_error", "steps_cyl_version",
-    "STEPS_SUM_COMPENSATED", "STEPS_SUM_PLAIN", "STEPS_SUM_PAIRWISE", "STEPS_MAX_NIMG", "STEPS_MLP_PARAMS",
+    "STEPS_SUM_COMPENSATED", "STEPS_SUM_PLAIN", "STEPS_SUM_PAIRWISE", "STEPS_MAX_NIMG", "STEPS_MAX_N", "STEPS_MLP_PARAMS",
     "steps_cyl_mlp_create", "steps_cyl_mlp_destroy", "steps_cyl_mlp_get_params",
     "steps_cyl_mlp_set_params", "steps_cyl_mlp_forward", "steps_cyl_mlp_grad",
     "steps_cyl_mlp_samples", "steps_cyl_mlp_train", "steps_cyl_mlp_save", "steps_cyl_mlp_load",
@@ -45,6 +45,7 @@ STEPS_SUM_COMPENSATED = 0
 STEPS_SUM_PLAIN = 1
 STEPS_SUM_PAIRWISE = 2
 STEPS_MAX_NIMG = 4096
+STEPS_MAX_N = 1 << 29
 STEPS_MLP_PARAMS = 12802
 
 

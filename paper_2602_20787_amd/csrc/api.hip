@@ -20,12 +20,12 @@ int check_common(const void *pos, const void *mass, const void *eps, int64_t N, 
                  int n_img, const void *targets, int64_t n_targets, const void *out_acc) {
     if (!pos || !mass || !eps) return fail(STEPS_EINVAL, "pos, mass and eps must be non-null");
     if (!out_acc) return fail(STEPS_EINVAL, "out_acc must be non-null");
-    if (N < 1 || N > INT32_MAX) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^31-1]", (long long)N);
+    if (N < 1 || N > STEPS_MAX_N) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^29]", (long long)N);
     if (!finite_positive(L)) return fail(STEPS_EINVAL, "L must be finite and > 0");
     if (n_img < 0 || n_img > STEPS_MAX_NIMG)
         return fail(STEPS_EINVAL, "n_img=%d outside [0, %d]", n_img, STEPS_MAX_NIMG);
-    if (n_targets < 1 || n_targets > INT32_MAX)
-        return fail(STEPS_EINVAL, "n_targets=%lld outside [1, 2^31-1]", (long long)n_targets);
+    if (n_targets < 1 || n_targets > STEPS_MAX_N)
+        return fail(STEPS_EINVAL, "n_targets=%lld outside [1, 2^29]", (long long)n_targets);
     if (!targets && n_targets != N)
         return fail(STEPS_EINVAL, "targets is NULL, so n_targets must equal N");
     return STEPS_OK;

@@ -371,7 +371,7 @@ STEPS_API int steps_cyl_history_factors(const double *t, const double *a, int64_
 STEPS_API int steps_cyl_compensation(const double *pos, int64_t N, double R_cyl, double Z, double rho0,
                                      double *out, hipStream_t stream) {
     if (!pos || !out) return fail(STEPS_EINVAL, "pos and out must be non-null");
-    if (N < 1 || N > INT32_MAX) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^31-1]", (long long)N);
+    if (N < 1 || N > STEPS_MAX_N) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^29]", (long long)N);
     if (!finite_positive(R_cyl) || !(Z > 0.0) || !std::isfinite(rho0) || rho0 < 0.0)
         return fail(STEPS_EINVAL, "need R_cyl > 0 finite, Z > 0 (infinity allowed) and rho0 >= 0");
     int rc = require_device();
@@ -387,7 +387,7 @@ STEPS_API int steps_cyl_kdk_step(double *pos, double *mom, const double *mass, c
                                  hipStream_t stream) {
     if (!pos || !mom || !mass || !eps || !acc_inout)
         return fail(STEPS_EINVAL, "pos, mom, mass, eps and acc_inout must be non-null");
-    if (N < 1 || N > INT32_MAX) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^31-1]", (long long)N);
+    if (N < 1 || N > STEPS_MAX_N) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^29]", (long long)N);
     if (!finite_positive(L)) return fail(STEPS_EINVAL, "L must be finite and > 0");
     int rc = check_params(params);
     if (rc) return rc;

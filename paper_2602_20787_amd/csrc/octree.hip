@@ -37,7 +37,8 @@
 #include <cmath>
 #include <vector>
 
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "table_pair.h"
 
@@ -117,8 +118,8 @@ hipError_t ensure_particles(steps_cyl_tree *t, int64_t n) {
     if (e != hipSuccess) return e;
     // scratch of the library sort and scan, sized for c items
     size_t b1 = 0, b2 = 0;
-    e = hipcub::DeviceRadixSort::SortPairs(nullptr, b1, t->key_in, t->key_out, t->idx_in, t->idx_out, (int)c, 0, 63);
-    if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(nullptr, b2, t->fs, t->ss, (int)c);
+    e = rocprim::radix_sort_pairs(nullptr, b1, t->key_in, t->key_out, t->idx_in, t->idx_out, (int)c, 0, 63);
+    if (e == hipSuccess) e = rocprim::inclusive_scan(nullptr, b2, t->fs, t->ss, (size_t)c, rocprim::plus<int>(), 0);
     if (e != hipSuccess) return e;
     const size_t need = std::max(b1, b2);
     if (need > t->cub_bytes) {
@@ -174,9 +175,9 @@ hipError_t ensure_cells(steps_cyl_tree *t, int64_t n, hipStream_t stream) {
     t->cap_cells = c;
     // the cell sort's and the cell scan's scratch grow with the cell count
     size_t b = 0, b2 = 0;
-    e = hipcub::DeviceRadixSort::SortPairs(nullptr, b, t->c_key_in, t->c_key_out, t->c_id_in, t->c_id_out, (int)c, 0,
+    e = rocprim::radix_sort_pairs(nullptr, b, t->c_key_in, t->c_key_out, t->c_id_in, t->c_id_out, (int)c, 0,
                                            37);
-    if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(nullptr, b2, t->g_cnt, t->g_off, (int)c);
+    if (e == hipSuccess) e = rocprim::inclusive_scan(nullptr, b2, t->g_cnt, t->g_off, (size_t)c, rocprim::plus<int>(), 0);
     if (e != hipSuccess) return e;
     b = std::max(b, b2);
     if (b > t->cub_bytes) {
@@ -715,7 +716,7 @@ int build(steps_cyl_tree *t, const double *pos, const double *mass, const double
                        t->key_in, t->idx_in);
     TRY(hipGetLastError());
     size_t bytes = t->cub_bytes;
-    TRY(hipcub::DeviceRadixSort::SortPairs(t->cub_tmp, bytes, t->key_in, t->key_out, t->idx_in, t->idx_out, n, 0, 63,
+    TRY(rocprim::radix_sort_pairs(t->cub_tmp, bytes, t->key_in, t->key_out, t->idx_in, t->idx_out, n, 0, 63,
                                            stream));
     const int root_leaf = (n <= t->leaf_size) ? 1 : 0;
     hipLaunchKernelGGL(gather_kernel, dim3(blocks(N)), dim3(kBlock), 0, stream, t->idx_out, n, t->tx, t->ty, t->tz,
@@ -736,9 +737,9 @@ int build(steps_cyl_tree *t, const double *pos, const double *mass, const double
                            t->fe);
         TRY(hipGetLastError());
         bytes = t->cub_bytes;
-        TRY(hipcub::DeviceScan::InclusiveSum(t->cub_tmp, bytes, t->fs, t->ss, n, stream));
+        TRY(rocprim::inclusive_scan(t->cub_tmp, bytes, t->fs, t->ss, (size_t)(n), rocprim::plus<int>(), stream));
         bytes = t->cub_bytes;
-        TRY(hipcub::DeviceScan::InclusiveSum(t->cub_tmp, bytes, t->fe, t->se, n, stream));
+        TRY(rocprim::inclusive_scan(t->cub_tmp, bytes, t->fe, t->se, (size_t)(n), rocprim::plus<int>(), stream));
         int m = 0;
         TRY(hipMemcpyAsync(&m, t->ss + (n - 1), sizeof(int), hipMemcpyDeviceToHost, stream));
         TRY(hipStreamSynchronize(stream));
@@ -760,7 +761,7 @@ int build(steps_cyl_tree *t, const double *pos, const double *mass, const double
         int any = 0;
         if (level < kLevels) {
             bytes = t->cub_bytes;
-            TRY(hipcub::DeviceScan::InclusiveSum(t->cub_tmp, bytes, t->act, t->fs, n, stream));
+            TRY(rocprim::inclusive_scan(t->cub_tmp, bytes, t->act, t->fs, (size_t)(n), rocprim::plus<int>(), stream));
             TRY(hipMemcpyAsync(&any, t->fs + (n - 1), sizeof(int), hipMemcpyDeviceToHost, stream));
             TRY(hipStreamSynchronize(stream));
         }
@@ -786,7 +787,7 @@ int build(steps_cyl_tree *t, const double *pos, const double *mass, const double
                        t->c_key_in, t->c_id_in);
     TRY(hipGetLastError());
     bytes = t->cub_bytes;
-    TRY(hipcub::DeviceRadixSort::SortPairs(t->cub_tmp, bytes, t->c_key_in, t->c_key_out, t->c_id_in, t->c_id_out,
+    TRY(rocprim::radix_sort_pairs(t->cub_tmp, bytes, t->c_key_in, t->c_key_out, t->c_id_in, t->c_id_out,
                                            total, 0, 37, stream));
     hipLaunchKernelGGL(dfs_cells_kernel, dim3(blocks(total)), dim3(kBlock), 0, stream, total, n, t->c_key_out,
                        t->c_id_out, t->c_start, t->c_count, t->c_level, t->c_leaf, t->c_m, t->c_mx, t->c_my, t->c_mz,
@@ -797,7 +798,7 @@ int build(steps_cyl_tree *t, const double *pos, const double *mass, const double
     hipLaunchKernelGGL(group_count_kernel, dim3(blocks(total)), dim3(kBlock), 0, stream, t->cells, total, t->g_cnt);
     TRY(hipGetLastError());
     bytes = t->cub_bytes;
-    TRY(hipcub::DeviceScan::InclusiveSum(t->cub_tmp, bytes, t->g_cnt, t->g_off, total, stream));
+    TRY(rocprim::inclusive_scan(t->cub_tmp, bytes, t->g_cnt, t->g_off, (size_t)(total), rocprim::plus<int>(), stream));
     hipLaunchKernelGGL(group_write_kernel, dim3(blocks(total)), dim3(kBlock), 0, stream, t->cells, total, t->g_cnt,
                        t->g_off, t->g_start, t->g_count);
     TRY(hipGetLastError());
@@ -857,7 +858,7 @@ int walk(steps_cyl_tree *t, const steps_cyl_table *table, int order, double L, d
 int check_common(const double *pos, const double *mass, const double *eps, int64_t N, double L, double R_dom,
                  const steps_cyl_table *table, int order, double theta) {
     if (!pos || !mass || !eps || !table) return fail(STEPS_EINVAL, "pos, mass, eps and table must be non-null");
-    if (N < 1 || N > (int64_t)1 << 30) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^30]", (long long)N);
+    if (N < 1 || N > STEPS_MAX_N) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^29]", (long long)N);
     if (!finite_positive(L) || !finite_positive(R_dom)) return fail(STEPS_EINVAL, "L and R_dom must be finite and > 0");
     if (order != 1 && order != 2) return fail(STEPS_EINVAL, "order=%d: 1 (CIC) or 2 (TSC)", order);
     if (!std::isfinite(theta) || theta < 0.0) return fail(STEPS_EINVAL, "theta must be finite and >= 0");

@@ -393,10 +393,10 @@ STEPS_API int steps_cyl_forces_table(const double *pos, const double *mass, cons
                                      int64_t n_targets, float *out_acc, float *out_pot, hipStream_t stream) {
     if (!pos || !mass || !eps || !out_acc || !t)
         return fail(STEPS_EINVAL, "pos, mass, eps, out_acc and table must be non-null");
-    if (N < 1 || N > INT32_MAX) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^31-1]", (long long)N);
+    if (N < 1 || N > STEPS_MAX_N) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^29]", (long long)N);
     if (!finite_positive(L)) return fail(STEPS_EINVAL, "L must be finite and > 0");
     if (order != 1 && order != 2) return fail(STEPS_EINVAL, "order=%d: 1 (CIC) or 2 (TSC)", order);
-    if (n_targets < 1 || n_targets > INT32_MAX) return fail(STEPS_EINVAL, "n_targets out of range");
+    if (n_targets < 1 || n_targets > STEPS_MAX_N) return fail(STEPS_EINVAL, "n_targets out of range");
     if (!targets && n_targets != N) return fail(STEPS_EINVAL, "targets is NULL, so n_targets must equal N");
     int rc = require_device();
     if (rc) return rc;

@@ -5,7 +5,7 @@
 // the softened branch) coherent within a wave.  The order changes no result:
 // each target's sum runs over the sources in their own order and is written
 // to the target's own position in the list.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.h"
 #include "pair_f64.h"
@@ -57,7 +57,7 @@ int order_targets(const double *pos, int64_t N, double L, const int64_t *targets
     *perm = nullptr;
     const int n = (int)n_tgt;
     size_t cub = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, cub, (uint32_t *)nullptr, (uint32_t *)nullptr,
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, cub, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                       (int *)nullptr, (int *)nullptr, n, 0, 30, stream);
     if (e != hipSuccess) return hip_status(e, "target order");
     // partials, keys and indices (twice), the sort's scratch
@@ -75,7 +75,7 @@ int order_targets(const double *pos, int64_t N, double L, const int64_t *targets
     hipLaunchKernelGGL(order_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, pos, (int)N, L, partial,
                        targets, n, k_in, i_in);
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortPairs(tmp, cub, k_in, k_out, i_in, i_out, n, 0, 30, stream);
+    if (e == hipSuccess) e = rocprim::radix_sort_pairs(tmp, cub, k_in, k_out, i_in, i_out, n, 0, 30, stream);
     if (e != hipSuccess) {
         (void)hipFreeAsync(*scratch, stream);
         *scratch = nullptr;

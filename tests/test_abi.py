@@ -46,6 +46,7 @@ P = 8  # a non-null dummy address: never dereferenced because validation fails f
     ((P, P, P, 0, 1.0, 8, P, None, None), "N=0"),
     ((P, P, P, -5, 1.0, 8, P, None, None), "N=-5"),
     ((P, P, P, 2 ** 31, 1.0, 8, P, None, None), "N="),
+    ((P, P, P, 2 ** 29 + 1, 1.0, 8, P, None, None), "N=536870913"),
     ((P, P, P, 10, 0.0, 8, P, None, None), "L must"),
     ((P, P, P, 10, -1.0, 8, P, None, None), "L must"),
     ((P, P, P, 10, math.nan, 8, P, None, None), "L must"),
@@ -70,6 +71,15 @@ def test_subset_entry_points_reject_invalid_arguments(fn):
     assert f(P, P, P, 10, 1.0, 8, P, 0, *extra, P, None, None) == sc.STEPS_EINVAL
     # missing output
     assert f(P, P, P, 10, 1.0, 8, P, 3, *extra, None, None, None) == sc.STEPS_EINVAL
+
+
+def test_particle_count_cap_keeps_soa_offsets_in_int32():
+    # the kernels address component c of particle i at c*N + i in 32-bit
+    # arithmetic (c <= 3); the cap keeps the largest offset representable
+    assert sc.STEPS_MAX_N == 2 ** 29
+    assert 3 * sc.STEPS_MAX_N + (sc.STEPS_MAX_N - 1) <= 2 ** 31 - 1
+    text = open(HEADER).read()
+    assert "#define STEPS_MAX_N (1LL << 29)" in text
 
 
 def test_forces_ex_rejects_unknown_mode():
