@@ -3,21 +3,31 @@
 One step is one full force + potential evaluation (steps_cyl_forces) of
 N = 2^20 particles of the stereographic cylinder load (seed 0) with images
 |n| <= 8 along z: N^2 = 1.1e12 pair interactions, delivered by evaluating
-each unordered pair once.  The per-target kernel over all targets is timed
-once beside it.  A second leg ("learned") compares the learned far-image
-correction with the exact |n| <= 1024 sum at --learned-n particles (time,
-speedup, accuracy against the FP64 reference).  Inputs are resident in HBM
-before the timed region; the timed region is bracketed by stream
-synchronisation and measured with HIP events on the stream the kernel runs
-on.
+each unordered pair once.  Inputs are resident in HBM before the timed
+region; the timed region is bracketed by stream synchronisation and measured
+with HIP events on the stream the kernels run on.
 
-Prints one JSON line.  ``value`` is G pair-interactions/s (N^2 / t / 1e9) and
-``pct_fp32_vector_peak`` is F_pair N^2 / t against the FP32 vector peak,
-F_pair = 28 + 20 n_img per pair with the potential (25 + 18 n_img without).
-The roofline object prices the pair terms the kernel actually evaluates
-(about N^2 / 2, each F_pair plus 9 FLOP of reaction) against the same peak;
-the CPU baseline is the FP64 oracle timed on a bounded sample of targets on
-the host's cores.
+Secondary legs (each timed as the median of several runs after a warm-up):
+  * one_sided: the per-target kernel over all targets;
+  * precision_c3: FP32 pair terms with Kahan per-target sums, with plain FP32
+    sums and the pairwise FP64-sum path against the FP64 GPU reference on
+    8192 targets of the same load (max, rms and 99.9th-percentile relative
+    acceleration error, potential error), the reference itself against the
+    CPU oracle on 256 of them;
+  * learned: at --learned-n particles (default 2^20), the learned far-image
+    correction (every unordered pair once), the 144 x 128 correction tables
+    (CIC, TSC) and the exact |n| <= 1024 sum (per-target kernel on a subset of
+    targets, scaled to all targets), with accuracy against the FP64 |n| <= 1024
+    reference on 1024 targets;
+  * octree and table builds.
+
+Prints one JSON line.  ``value`` is G pair-interactions/s (N^2 / t / 1e9).
+The roofline object prices the pair terms the kernels actually evaluate
+(about N^2 / 2, each F_pair = 28 + 20 n_img FLOP plus 9 FLOP of reaction)
+against the FP32 vector peak; ``pct_fp32_vector_peak_n2_count`` is the
+metric's N^2 count (it credits the pairs that symmetry skips).  The CPU
+baseline is the FP64 oracle timed on a bounded sample of targets on the
+host's cores.
 """
 from __future__ import annotations
 
@@ -37,12 +47,13 @@ PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak (packed FMA
 PEAK_FP32_UNPACKED = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 
 
-# HBM bytes per launch of forces_pairwise_kernel<8,true,0,false> at N = 2^20 from the
-# rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter
-# reads for a 256 MiB copy (profiles/forces_pairwise_N1M_nimg8_counters.md).
-# Valid only for the kernel sources they were measured on (hash below).
-TRAFFIC_EXACT_N1M = {"bytes": 2.5823e+10, "fetch_scale": 1.99969, "write_scale": 1.0,
-                     "sources_sha256_16": "7b845ea30863bb94"}
+# HBM bytes per call of steps_cyl_forces at N = 2^20, |n| <= 8 (all its
+# launches) from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by
+# what the counter reads for a 256 MiB copy
+# (profiles/forces_pairwise_N1M_nimg8_counters.md).  Valid only for the
+# kernel sources they were measured on (hash below); None until measured.
+TRAFFIC_EXACT_N1M = {"bytes": None, "fetch_scale": 1.99969, "write_scale": 1.0,
+                     "sources_sha256_16": None}
 TRAFFIC_SOURCES = ["forces_pairwise.hip", "pair_fp32.h", "pair_f64.h", "target_order.hip"]
 
 
@@ -66,11 +77,48 @@ PAIRWISE_GROUP = 1024
 
 
 def pairwise_evaluations(N):
-    """Pair terms the pairwise kernel evaluates: every ordered pair inside a
+    """Pair terms the pairwise kernels evaluate: every ordered pair inside a
     group of PAIRWISE_GROUP particles, every pair across groups once."""
     full, tail = divmod(N, PAIRWISE_GROUP)
     inner = full * PAIRWISE_GROUP ** 2 + tail ** 2
     return (N * N + inner) // 2
+
+
+def meeting_launches(N):
+    """Launches of the meeting kernel per call: G' - 1 tournament rounds,
+    G' the group count rounded up to even."""
+    G = (N + PAIRWISE_GROUP - 1) // PAIRWISE_GROUP
+    return G + (G & 1) - 1
+
+
+def timed(fn, runs, stream):
+    """Median and all durations (ms) of ``runs`` calls of fn(), each
+    bracketed by HIP events on ``stream``."""
+    import numpy as np
+    import torch
+    ms = []
+    for _ in range(runs):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.median(ms)), ms
+
+
+def err_stats(a, ref, pot=None, pot_ref=None):
+    """Max, rms and 99.9th percentile of |a - ref| / |ref| per target, and the
+    largest relative potential error."""
+    import numpy as np
+    e = np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    out = {"max": float(f"{e.max():.3e}"), "rms": float(f"{math.sqrt(np.mean(e ** 2)):.3e}"),
+           "p99_9": float(f"{np.percentile(e, 99.9):.3e}"), "median": float(f"{np.median(e):.3e}")}
+    if pot is not None:
+        pe = np.abs(pot - pot_ref) / np.abs(pot_ref)
+        out["pot_max"] = float(f"{pe.max():.3e}")
+    return out
 
 
 def exact_leg(args, dev):
@@ -108,24 +156,22 @@ def exact_leg(args, dev):
     ms = float(np.mean(step_ms))
     pairs = float(N) * float(N)
     value = pairs / (ms * 1e-3) / 1e9
-    # the kernel evaluates each unordered pair once (groups of PAIRWISE_GROUP
+    # the kernels evaluate each unordered pair once (groups of PAIRWISE_GROUP
     # particles: all ordered pairs inside a group, each cross pair once) and
-    # applies it to both particles
+    # apply it to both particles; the whole call (ordering, staging, the self
+    # launch, the tournament's launches and the final pass) is the time base
     evals = pairwise_evaluations(N)
     achieved = evals * (flops_per_pair(n_img) + REACTION_FLOPS) / (ms * 1e-3)
     print(f"[bench] per-step ms {['%.1f' % x for x in step_ms]} wall {wall:.2f}s",
           file=sys.stderr, flush=True)
     # the per-target kernel (steps_cyl_forces_ex over all targets), for comparison
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     acc1 = torch.empty_like(acc)
     pot1 = torch.empty_like(pot)
-    e0.record(stream)
-    sc.steps_cyl_forces_ex(pos, m, e, p.L, n_img, out_acc=acc1, out_pot=pot1, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms1 = e0.elapsed_time(e1)
-    print(f"[bench] one-sided kernel {ms1:.1f} ms", file=sys.stderr, flush=True)
+    ms1, ms1_all = timed(lambda: sc.steps_cyl_forces_ex(pos, m, e, p.L, n_img, out_acc=acc1, out_pot=pot1,
+                                                        stream=stream), args.secondary_runs, stream)
+    print(f"[bench] one-sided kernel {ms1:.1f} ms (median of {len(ms1_all)})", file=sys.stderr, flush=True)
+    traffic_ok = (N == 1 << 20 and n_img == 8 and TRAFFIC_EXACT_N1M["bytes"] is not None
+                  and exact_sources_hash() == TRAFFIC_EXACT_N1M["sources_sha256_16"])
 
     out = {
         "metric": METRIC,
@@ -148,29 +194,29 @@ def exact_leg(args, dev):
             "N": N, "n_img": n_img, "L": 1.0, "potential": True,
         },
         "image_terms_per_s": round(pairs * (2 * n_img + 1) / (ms * 1e-3), 1),
-        # the metric's own definition: F_pair x N^2 / t against the peak
-        "pct_fp32_vector_peak": round(100.0 * flops_per_pair(n_img) * pairs / (ms * 1e-3)
-                                      / PEAK_FP32_VECTOR, 2),
         "roofline": {
             "bound": "alu",
             "achieved": round(achieved / 1e12, 3),
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_VECTOR, 4),
-            "traffic": (TRAFFIC_EXACT_N1M["bytes"]
-                        if (N == 1 << 20 and n_img == 8
-                            and exact_sources_hash() == TRAFFIC_EXACT_N1M["sources_sha256_16"])
-                        else None),
-            "traffic_unit": "B per launch (HBM, counter-calibrated)",
+            "traffic": TRAFFIC_EXACT_N1M["bytes"] if traffic_ok else None,
+            "traffic_unit": "B per call (HBM, counter-calibrated)",
             "flops_per_evaluation": flops_per_pair(n_img) + REACTION_FLOPS,
             "evaluations": evals,
+            "time_base": "whole steps_cyl_forces call",
+            "meeting_launches_per_call": meeting_launches(N),
             "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_UNPACKED, 4),
-            "kernel": "forces_pairwise_kernel<8,true,0,false>",
+            "kernel": f"forces_pairwise_kernel<{n_img},true,0,false,true> (tournament meetings; "
+                      f"plus one self launch <{n_img},true,0,false,false>)",
         },
+        # the metric's N^2 count (F_pair for every ordered pair, including the
+        # half that symmetry skips): a dense-equivalent figure
+        "pct_fp32_vector_peak_n2_count": round(100.0 * flops_per_pair(n_img) * pairs / (ms * 1e-3)
+                                               / PEAK_FP32_VECTOR, 2),
         "one_sided": {
-            "ms": round(ms1, 3), "G_pairs_per_s": round(pairs / (ms1 * 1e-3) / 1e9, 3),
-            "pct_fp32_vector_peak": round(100.0 * flops_per_pair(n_img) * pairs / (ms1 * 1e-3)
-                                          / PEAK_FP32_VECTOR, 2),
+            "ms": round(ms1, 3), "runs": len(ms1_all), "G_pairs_per_s": round(pairs / (ms1 * 1e-3) / 1e9, 3),
+            "frac_fp32_vector_peak": round(flops_per_pair(n_img) * pairs / (ms1 * 1e-3) / PEAK_FP32_VECTOR, 4),
             "kernel": "forces_exact_kernel<8,true,true> (steps_cyl_forces_ex, all targets)",
         },
     }
@@ -195,25 +241,66 @@ def exact_leg(args, dev):
             "sample": f"{k} random targets x all {N} sources, |n|<={n_img}, FP64, {dt:.1f} s",
         }
         a = acc.cpu().numpy().astype(np.float64)[:, tg]
-        err = np.linalg.norm(a - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)
-        perr = np.abs(pot.cpu().numpy().astype(np.float64)[tg] - p_ref) / np.abs(p_ref)
-        out["max_rel_err"] = float(f"{err.max():.3e}")
-        out["rms_rel_err"] = float(f"{math.sqrt(np.mean(err ** 2)):.3e}")
-        out["max_rel_pot_err"] = float(f"{perr.max():.3e}")
+        st = err_stats(a, a_ref, pot.cpu().numpy().astype(np.float64)[tg], p_ref)
+        out["max_rel_err"] = st["max"]
+        out["rms_rel_err"] = st["rms"]
+        out["p99_9_rel_err"] = st["p99_9"]
+        out["max_rel_pot_err"] = st["pot_max"]
         out["err_sample_targets"] = k
+    if args.precision_targets:
+        out["precision_c3"] = precision_leg(args, dev, p, pos, m, e, acc, pot)
     return out
 
 
-def _chunks(n, parts):
-    step = (n + parts - 1) // parts
-    return [(a, min(n, a + step)) for a in range(0, n, step)]
+def precision_leg(args, dev, p, pos, m, e, acc, pot):
+    """C3's precision study on the exact leg's load: FP32 pair terms with
+    Kahan-compensated per-target sums, with plain FP32 per-target sums, and
+    the pairwise path (FP64 sums; the exact leg's result), each against the
+    FP64 GPU reference on the same targets; the reference against the CPU
+    oracle on a subset."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2602_20787_amd as sc
+    N, n_img = p.N, args.n_img
+    k = min(args.precision_targets, N)
+    tg = synth.target_sample(N, k, seed=31)
+    t = torch.from_numpy(tg).to(dev)
+    print(f"[bench] precision study on {k} targets", file=sys.stderr, flush=True)
+    ref, ref_pot = sc.steps_cyl_forces_f64(pos, m, e, p.L, n_img, targets=t)
+    comp, comp_pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, n_img, targets=t, mode=sc.STEPS_SUM_COMPENSATED)
+    plain, plain_pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, n_img, targets=t, mode=sc.STEPS_SUM_PLAIN)
+    torch.cuda.synchronize()
+    r, rp = ref.cpu().numpy(), ref_pot.cpu().numpy()
+
+    def host(x):
+        return x.double().cpu().numpy()
+    out = {
+        "N": N, "n_img": n_img, "targets": k,
+        "reference": "FP64 GPU direct sum (steps_cyl_forces_f64) on the same targets",
+        "compensated_fp32": err_stats(host(comp), r, host(comp_pot), rp),
+        "plain_fp32": err_stats(host(plain), r, host(plain_pot), rp),
+        "pairwise_fp64_sums": err_stats(host(acc)[:, tg], r, host(pot)[tg], rp),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        ko = min(args.precision_oracle_targets, k)
+        sub = tg[:ko]
+        a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, n_img, targets=sub)
+        st = err_stats(r[:, :ko], a_ref, rp[:ko], p_ref)
+        out["reference_vs_oracle"] = {"targets": ko, "max": st["max"], "pot_max": st["pot_max"]}
+    print(f"[bench] precision {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def learned_leg(args, dev):
-    """Learned correction vs exact |n| <= 1024 at N = args.learned_n: time of
-    a full evaluation of each (targets in chunks, so no launch runs longer
-    than ~2 minutes), speedup, and accuracy of both against the FP64 GPU
-    reference on 1024 targets."""
+    """Far images at N = args.learned_n: the learned correction and the
+    144 x 128 correction tables over all particles (every unordered pair
+    once), and the exact |n| <= 1024 sum and the learned correction with the
+    per-target kernels on a subset of targets, scaled to all N targets (the
+    per-target cost does not depend on the target).  Accuracy of each against
+    the FP64 |n| <= 1024 reference on 1024 targets (the first of the subset)."""
     import numpy as np
     import torch
 
@@ -227,107 +314,82 @@ def learned_leg(args, dev):
     e = torch.from_numpy(p.eps).to(dev)
     net = sc.Mlp.load(os.path.join(ROOT, "paper_2602_20787_amd", "data", "correction_net.bin"))
     stream = torch.cuda.current_stream(dev)
-    acc_l = torch.empty((3, N), dtype=torch.float32, device=dev)
-    acc_x = torch.empty((3, N), dtype=torch.float32, device=dev)
-    # chunk so that one exact |n| <= 1024 launch stays near a minute at most
-    parts = max(1, int(math.ceil(float(N) * N / 2.0e11)))
-    ranges = _chunks(N, parts)
-    idx = [torch.arange(a, b, dtype=torch.int64, device=dev) for a, b in ranges]
+    k_sub = min(N, args.learned_subset)
+    sub_np = synth.target_sample(N, k_sub, seed=7)
+    sub = torch.from_numpy(sub_np).to(dev)
+    acc_t = sub[:1024]
+    pairs = float(N) * N
 
-    def run(kind):
-        total = 0.0
-        for (a, b), t in zip(ranges, idx):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            if kind == "learned":
-                o, _ = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=t,
-                                                      potential=False, stream=stream)
-                acc_l[:, a:b] = o
-            else:
-                o, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 1024, targets=t, potential=False,
-                                              stream=stream)
-                acc_x[:, a:b] = o
-            e1.record(stream)
-            torch.cuda.synchronize()
-            total += e0.elapsed_time(e1)
-            print(f"[bench] {kind} N={N} targets {a}..{b} done ({total / 1e3:.1f} s)",
-                  file=sys.stderr, flush=True)
-        return total
-
+    # warm-ups (code objects, the network's first use) on a few targets
+    sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=acc_t, potential=False)
     table = sc.CorrectionTable(128, 144, 6.4, 1024)
-    acc_t = {1: torch.empty((3, N), dtype=torch.float32, device=dev),
-             2: torch.empty((3, N), dtype=torch.float32, device=dev)}
-
-    def run_table(order):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        sc.steps_cyl_forces_table(pos, m, e, p.L, table, order=order, potential=False,
-                                  out_acc=acc_t[order], stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        print(f"[bench] table order {order} N={N} done ({ms / 1e3:.1f} s)", file=sys.stderr, flush=True)
-        return ms
-
-    sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=idx[0][:1024], potential=False)
-    sc.steps_cyl_forces_table(pos, m, e, p.L, table, order=1, targets=idx[0][:1024], potential=False)
+    sc.steps_cyl_forces_table(pos, m, e, p.L, table, order=1, targets=acc_t, potential=False)
     torch.cuda.synchronize()
-    ms_t = {o: run_table(o) for o in (1, 2)}
-    ms_l = run("learned")
-    ms_x = run("exact")
-    # the learned correction over all particles at once: each unordered pair once
-    acc_pw = torch.empty((3, N), dtype=torch.float32, device=dev)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    sc.steps_cyl_forces_learned(pos, m, e, p.L, net, out_acc=acc_pw, potential=False, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_lp = e0.elapsed_time(e1)
-    print(f"[bench] learned pairwise N={N} done ({ms_lp / 1e3:.1f} s)", file=sys.stderr, flush=True)
-    t = torch.from_numpy(synth.target_sample(N, 1024, seed=7)).to(dev)
-    ref, _ = sc.steps_cyl_forces_f64(pos, m, e, p.L, 1024, targets=t, potential=False)
-    a8, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t, potential=False)
+
+    acc_lp = torch.empty((3, N), dtype=torch.float32, device=dev)
+    ms_lp, ms_lp_all = timed(lambda: sc.steps_cyl_forces_learned(pos, m, e, p.L, net, out_acc=acc_lp,
+                                                                 potential=False, stream=stream),
+                             args.learned_runs, stream)
+    print(f"[bench] learned pairwise N={N}: {ms_lp / 1e3:.2f} s (median of {len(ms_lp_all)})",
+          file=sys.stderr, flush=True)
+    acc_tab = {}
+    ms_tab = {}
+    for order in (1, 2):
+        acc_tab[order] = torch.empty((3, N), dtype=torch.float32, device=dev)
+        ms_tab[order], _ = timed(lambda: sc.steps_cyl_forces_table(pos, m, e, p.L, table, order=order,
+                                                                   potential=False, out_acc=acc_tab[order],
+                                                                   stream=stream),
+                                 args.secondary_runs, stream)
+        print(f"[bench] table order {order} N={N}: {ms_tab[order] / 1e3:.2f} s", file=sys.stderr, flush=True)
+    acc_ls = torch.empty((3, k_sub), dtype=torch.float32, device=dev)
+    acc_xs = torch.empty((3, k_sub), dtype=torch.float32, device=dev)
+    ms_ls, _ = timed(lambda: sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=sub, potential=False,
+                                                            out_acc=acc_ls, stream=stream),
+                     args.learned_runs, stream)
+    print(f"[bench] learned per-target {k_sub} targets: {ms_ls:.1f} ms", file=sys.stderr, flush=True)
+    ms_xs, _ = timed(lambda: sc.steps_cyl_forces_ex(pos, m, e, p.L, 1024, targets=sub, potential=False,
+                                                    out_acc=acc_xs, stream=stream),
+                     args.learned_runs, stream)
+    print(f"[bench] exact |n|<=1024 per-target {k_sub} targets: {ms_xs:.1f} ms", file=sys.stderr, flush=True)
+    scale = N / k_sub
+    ref, _ = sc.steps_cyl_forces_f64(pos, m, e, p.L, 1024, targets=acc_t, potential=False)
+    a8, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=acc_t, potential=False)
     torch.cuda.synchronize()
     r = ref.cpu().numpy()
 
     def err(a):
-        a = a.double().cpu().numpy()
-        v = np.linalg.norm(a - r, axis=0) / np.linalg.norm(r, axis=0)
-        return float(f"{v.max():.3e}"), float(f"{np.median(v):.3e}")
+        return err_stats(a.double().cpu().numpy(), r)
 
-    el, ex, e8 = err(acc_l[:, t]), err(acc_x[:, t]), err(a8)
-    elp = err(acc_pw[:, t])
-    et = {o: err(acc_t[o][:, t]) for o in (1, 2)}
-    pairs = float(N) * N
-    net.close()
-    table.close()
-    return {
-        "N": N, "workload": f"stereographic cylinder load N={N} (seed 0): exact |n|<=1 + "
-                            "network (or 144x128 table) correction for 2<=|n|<=1024 "
-                            "vs exact |n|<=1024",
-        "ms_learned": round(ms_l, 1), "ms_exact1024": round(ms_x, 1),
-        "learned_G_pairs_per_s": round(pairs / (ms_l * 1e-3) / 1e9, 3),
-        "exact1024_G_pairs_per_s": round(pairs / (ms_x * 1e-3) / 1e9, 3),
-        "speedup_learned_vs_exact1024": round(ms_x / ms_l, 2),
-        "learned_pairwise": {
-            "ms": round(ms_lp, 1), "G_pairs_per_s": round(pairs / (ms_lp * 1e-3) / 1e9, 3),
-            "speedup_vs_per_target_learned": round(ms_l / ms_lp, 2),
-            "max_rel_err": elp[0], "median_rel_err": elp[1],
-        },
-        "err_vs_f64_exact1024_targets": 1024,
-        "learned_max_rel_err": el[0], "learned_median_rel_err": el[1],
-        "exact1024_fp32_max_rel_err": ex[0], "exact8_max_rel_err": e8[0],
+    out = {
+        "N": N,
+        "workload": f"stereographic cylinder load N={N} (seed 0): exact |n|<=1 + network (or 144x128 "
+                    f"table) for 2<=|n|<=1024 over all particles (each unordered pair once), against "
+                    f"exact |n|<=1024; the per-target times are measured on {k_sub} random targets and "
+                    f"scaled by N/{k_sub} (per-target cost is the same for every target)",
+        "learned_pairwise": {"ms": round(ms_lp, 1), "runs": len(ms_lp_all),
+                             "G_pairs_per_s": round(pairs / (ms_lp * 1e-3) / 1e9, 3),
+                             "err": err(acc_lp[:, acc_t])},
+        "learned_per_target": {"ms_all_targets": round(ms_ls * scale, 1), "ms_subset": round(ms_ls, 2),
+                               "G_pairs_per_s": round(pairs / (ms_ls * scale * 1e-3) / 1e9, 3),
+                               "err": err(acc_ls[:, :1024])},
+        "exact1024_per_target": {"ms_all_targets": round(ms_xs * scale, 1), "ms_subset": round(ms_xs, 2),
+                                 "G_pairs_per_s": round(pairs / (ms_xs * scale * 1e-3) / 1e9, 3),
+                                 "err_fp32_vs_fp64": err(acc_xs[:, :1024])},
+        "speedup_learned_pairwise_vs_exact1024_per_target": round(ms_xs * scale / ms_lp, 2),
+        "speedup_learned_vs_exact1024_per_target_both": round(ms_xs / ms_ls, 2),
+        "exact8_err": err(a8),
+        "err_targets": 1024, "subset_targets": k_sub,
         "table_144x128": {
-            "cic_ms": round(ms_t[1], 1), "tsc_ms": round(ms_t[2], 1),
-            "cic_G_pairs_per_s": round(pairs / (ms_t[1] * 1e-3) / 1e9, 2),
-            "tsc_G_pairs_per_s": round(pairs / (ms_t[2] * 1e-3) / 1e9, 2),
-            "cic_max_rel_err": et[1][0], "cic_median_rel_err": et[1][1],
-            "tsc_max_rel_err": et[2][0], "tsc_median_rel_err": et[2][1],
+            "cic_ms": round(ms_tab[1], 1), "tsc_ms": round(ms_tab[2], 1), "runs": args.secondary_runs,
+            "cic_G_pairs_per_s": round(pairs / (ms_tab[1] * 1e-3) / 1e9, 2),
+            "tsc_G_pairs_per_s": round(pairs / (ms_tab[2] * 1e-3) / 1e9, 2),
+            "cic_err": err(acc_tab[1][:, acc_t]), "tsc_err": err(acc_tab[2][:, acc_t]),
         },
     }
+    net.close()
+    table.close()
+    print(f"[bench] learned leg {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def tree_leg(args, dev):
@@ -363,7 +425,7 @@ def tree_leg(args, dev):
     for quad, tr in ((False, tree), (True, quad_tree)):
         for theta in args.tree_theta:
             ms = []
-            for _ in range(3):
+            for _ in range(args.secondary_runs):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
@@ -387,10 +449,12 @@ def tree_leg(args, dev):
                                 "direct tabulated force on 4096 targets", "runs": rows}
 
 
-def table_build_leg(dev):
-    """Build times of the 144 x 128 correction tables: the direct sum over
-    10^7 images per side (the reference table of Fig. 2, which the paper
-    quotes at about 10^4 s) and the complete table from the Ewald split."""
+def table_build_leg(dev, runs):
+    """Build times of the 144 x 128 correction tables (median of ``runs``): the
+    direct sum over 10^7 images per side (the reference table of Fig. 2, which
+    the paper quotes at about 10^4 s) and the complete table from the Ewald
+    split."""
+    import numpy as np
     import torch
 
     import paper_2602_20787_amd as sc
@@ -400,10 +464,14 @@ def table_build_leg(dev):
                        ("ewald_complete", lambda: sc.CorrectionTable.ewald(128, 144, 6.4, 2.0, 5, 12))):
         make().close()  # first use: code objects and allocations
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        t = make()          # synchronous build
-        out[name + "_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
-        t.close()
+        ms = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            t = make()          # synchronous build
+            ms.append((time.perf_counter() - t0) * 1e3)
+            t.close()
+        out[name + "_ms"] = round(float(np.median(ms)), 2)
+    out["runs"] = runs
     out["image_terms_direct"] = 147 * 131 * 2 * (10 ** 7 - 1)
     print(f"[bench] table builds {out}", file=sys.stderr, flush=True)
     return out
@@ -437,8 +505,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--learned-n", type=int, default=1 << 17,
-                    help="particles of the learned-correction comparison (0 skips it)")
+    ap.add_argument("--learned-n", type=int, default=1 << 20,
+                    help="particles of the far-image comparison (0 skips it)")
+    ap.add_argument("--learned-subset", type=int, default=16384,
+                    help="targets of the per-target far-image timings (scaled to all targets)")
+    ap.add_argument("--learned-runs", type=int, default=3,
+                    help="timed runs of the learned and exact |n|<=1024 evaluations (median)")
+    ap.add_argument("--secondary-runs", type=int, default=5,
+                    help="timed runs of the other secondary legs (median)")
+    ap.add_argument("--precision-targets", type=int, default=8192,
+                    help="targets of the precision study (0 skips it)")
+    ap.add_argument("--precision-oracle-targets", type=int, default=256,
+                    help="of those, targets also computed by the CPU oracle")
     ap.add_argument("--exact-steps", type=int, default=None,
                     help="timed exact evaluations (default --steps); 0 skips the exact leg")
     ap.add_argument("--tree-n", type=int, default=1 << 20,
@@ -467,7 +545,7 @@ def main():
     if args.tree_n:
         out["octree"] = tree_leg(args, dev)
     if not args.no_table_build:
-        out["table_build"] = table_build_leg(dev)
+        out["table_build"] = table_build_leg(dev, args.secondary_runs)
     if args.copy_calib:
         out["copy_calib"] = copy_leg(dev)
     print(json.dumps(out), flush=True)

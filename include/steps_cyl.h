@@ -96,14 +96,15 @@ typedef enum {
  * set of (i, j)), so the reaction is the action with dx, dy and F_z negated
  * (F_z keeps its sign where both particles take the minimum image -L/2).
  * Arithmetic: pair separations and the z wrap in FP64, FP32 pair terms,
- * FP64 sums.  The sums meet through atomic additions whose order varies from
- * run to run, so repeated calls agree to one FP32 rounding step, not bit for
- * bit (steps_cyl_forces_ex with STEPS_SUM_COMPENSATED is the bitwise
- * deterministic per-target path).  Total momentum is conserved to the
+ * FP64 sums.  Groups of 1024 particles in spatial order meet in a fixed
+ * round-robin tournament (one launch per round, no atomics), so repeated
+ * calls on one device are bitwise equal.  Total momentum is conserved to the
  * rounding of the sums.  Scratch is stream-ordered (hipMallocAsync on
- * `stream`, released on it): about 80 bytes per particle plus the radix
- * sort's temporary storage.  Returns STEPS_OK, or STEPS_EINVAL /
- * STEPS_ENOMEM / STEPS_EHIP.
+ * `stream`, released on it): 32 bytes per particle for the records, 32 P
+ * bytes per particle for the sums (P in 1..16 workgroups per meeting, chosen
+ * to fill the device: 1 at N = 2^20) and 1 byte per particle for boxes, plus
+ * the spatial order's 16 bytes per particle and radix-sort storage.  Returns
+ * STEPS_OK, or STEPS_EINVAL / STEPS_ENOMEM / STEPS_EHIP.
  */
 int steps_cyl_forces(const double *pos, const double *mass, const double *eps,
                      int64_t N, double L, int n_img,

@@ -179,18 +179,21 @@ def forward(params, F, bf16=False):
     return h, cache
 
 
-def loss_and_grad(params, F, T, bf16=False):
+def loss_and_grad(params, F, T, bf16=False, round_dz=None):
     """Loss mean((o - T)^2) over both outputs and all samples, and its
     gradient with respect to the flat parameter vector.  With ``bf16`` the
     forward pass uses the rounded weights and activations and the backward
-    pass treats each rounding as the identity (straight-through); the
-    matrix products of layers 2-4 then take BF16-rounded pre-activation
-    gradients, as BF16 matrix units do (dW = bf16(dz) x^T and the propagated
-    gradient W^T bf16(dz)), while bias gradients and layers 1 and 5 use the
-    unrounded values."""
+    pass treats each rounding as the identity (straight-through).
+    ``round_dz`` (default: ``bf16``) also rounds the pre-activation gradients
+    of layers 2-4 to BF16 before their matrix products, as BF16 matrix units
+    do (dW = bf16(dz) x^T and the propagated gradient W^T bf16(dz)), while
+    bias gradients and layers 1 and 5 use the unrounded values; with
+    ``round_dz=False`` the backward pass is the plain FP64 one (the gradient
+    the rounded variant approximates)."""
+    if round_dz is None:
+        round_dz = bf16
     out, cache = forward(params, F, bf16)
     T = np.asarray(T, dtype=np.float64)
-    n = T.shape[1]
     diff = out - T
     loss = float(np.mean(diff * diff))
     g = 2.0 * diff / diff.size            # d loss / d out
@@ -198,7 +201,7 @@ def loss_and_grad(params, F, T, bf16=False):
     for k in range(DEPTH, -1, -1):
         x_in, Wq, z = cache[k]
         dz = g if k == DEPTH else g * silu_grad(z)
-        dzq = bf16_round(dz) if (bf16 and 1 <= k <= DEPTH - 1) else dz
+        dzq = bf16_round(dz) if (round_dz and 1 <= k <= DEPTH - 1) else dz
         dW = dzq @ x_in.T
         db = dz.sum(axis=1)
         grads.append((dW, db))

@@ -12,22 +12,36 @@
 //
 // Layout.  The particles are put in spatial (Morton) order and staged as
 // 32-byte records {x, y, z wrapped, m, h}; groups of 1024 consecutive
-// records (512 with a table) are the unit of work.  Group g pairs with itself (one-sided, all
-// ordered pairs, no reaction) and with the next K(g) groups modulo G, where
-// K = (G-1)/2 for odd G and G/2 - 1, plus one for the first half of the
-// groups, for even G; every unordered pair of groups then meets exactly
-// once.  The P workgroups of group g split its list of partner groups.
+// records (512 with a table) are the unit of work.  Each particle has P
+// slots of FP64 sums (x, y, z, potential).
 //
-// Workgroup.  256 threads own the particles of their group, 4 each (2 with a
-// table), in registers.  Partner records come through LDS in tiles of 256.  For each
-// source a thread adds the FP32 pair term to its own FP64 sums and the
-// reaction over its particles into one FP64 register set; the wave
-// reduces those 4 values over its 64 lanes (a reduce-scatter that leaves
-// one component per 16 lanes) and writes them to LDS; after the tile the 4
-// waves' values are added and the source's
-// reaction goes to FP64 device accumulators with atomic adds.  The owned
-// particles' sums join the same accumulators at the end, and a last pass
-// converts them to FP32 outputs at the particles' own positions.
+// Schedule (bitwise deterministic, no atomics).  A first launch pairs every
+// group with itself (one-sided, every ordered pair, the self pair skipped)
+// and initialises the slots.  Then G' - 1 launches (G' = G rounded up to
+// even) follow a round-robin tournament: in round r group G'-1 meets group
+// r and, for k = 1 .. G'/2 - 1, group (r + k) mod (G'-1) meets group
+// (r - k) mod (G'-1), so every unordered pair of groups meets exactly once
+// and no group appears twice in a round.  P workgroups share a meeting:
+// workgroup q holds group a's particles in registers and streams chunk q of
+// group b.  Within a launch the sums a workgroup touches are its own: slot q
+// of group a (a's sums from chunk q) and slot 0 of chunk q of group b (the
+// reactions), so every sum is a plain read-modify-write in an order fixed by
+// (N, P).  A last pass adds the slots in order and writes FP32 outputs at the
+// particles' own positions.
+//
+// Workgroup.  256 threads own the particles of group a, 4 each (2 with a
+// table), in registers; a wave's particles are 256 (128) consecutive
+// records.  Sources come through LDS in tiles of 256, as 64-source
+// sub-tiles: at step s lane l takes source (l + s) mod 64 of the sub-tile,
+// so that within a wave no two lanes meet the same source at once.  The
+// reaction on a source is summed in FP64 in an LDS slot that the wave's lanes
+// update in turn (64 steps visit every lane); after the tile the 4 waves'
+// slots are added in order.  A sub-tile whose bounding box is far from the
+// wave's (no pair closer than the sum of the largest softenings, no axial
+// separation near L/2) skips the softening and half-period screens; the pair
+// arithmetic is the same either way.
+#include <algorithm>
+
 #include "common.h"
 #include "pair_f64.h"
 #include "pair_fp32.h"
@@ -37,22 +51,29 @@ namespace steps {
 
 namespace {
 
-constexpr int kThreads = 256;           // 4 waves
-// particles per thread: 4 for the exact pair (fewer reactions to reduce and
-// add per pair); 2 with a table, whose gathers want the occupancy that the
-// smaller register set gives
+constexpr int kThreads = 256;  // 4 waves
+constexpr int kWaves = kThreads / 64;
+// particles per thread: 4 for the exact pair (the reaction's LDS update is
+// shared by more pairs); 2 with a table, whose gathers want the occupancy
+// that the smaller register set gives
 constexpr int particles_per_thread(int torder) { return torder > 0 ? 2 : 4; }
-constexpr int kTile = 256;              // sources per LDS tile
+constexpr int kTile = 256;  // sources per LDS tile
+constexpr int kSub = 64;    // sources per sub-tile (one wave's rotation)
+constexpr int kBox = 8;     // doubles per 64-record box
 
 struct PairwiseArgs {
-    const SrcRec *rec;  // [N] records in spatial order
-    double *acc;        // [4][N] sums in spatial order (x, y, z, potential)
+    const SrcRec *rec;   // [N] records in spatial order
+    const double *box;   // [ceil(N/64)][8] bounding boxes of aligned runs of 64 records
+    double *sum;         // [P][4][N] FP64 sums in spatial order (x, y, z, potential)
     double L, invL, halfL, tie;  // tie: |d| within this of L/2 takes the check
+    double far_h;                // largest softening sum for which the fast path is allowed
     float tie32;                 // FP32 screen for it: 0.5 L (1 - 1e-6), below every such |d|
     ImageConsts c;
-    TableView tv;       // far-image table (table paths only)
+    TableView tv;  // far-image table (table paths only)
     float invLf, invL2f;
-    int N, G, P;        // particles, groups, workgroups per group
+    int N, G, Gp;  // particles, groups, groups rounded up to even
+    int P, chunk;  // workgroups per meeting, sources per workgroup (multiple of 64)
+    int round;     // tournament round (launches of the meetings)
 };
 
 // Exact band 2 <= |n| <= n_far of one pair in one lane (delta = d/L signed,
@@ -75,7 +96,7 @@ __device__ __noinline__ void band_serial(float delta, float r, int n_far, float 
 }
 
 __global__ void stage_kernel(const double *pos, const double *mass, const double *eps, int N, double L,
-                             const int *perm, SrcRec *rec, double *acc) {
+                             const int *perm, SrcRec *rec) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const int p = perm[k];
@@ -86,22 +107,59 @@ __global__ void stage_kernel(const double *pos, const double *mass, const double
     r.m = (float)mass[p];
     r.h = (float)eps[p];
     rec[k] = r;
-    acc[k] = 0.0;
-    acc[N + k] = 0.0;
-    acc[2 * (int64_t)N + k] = 0.0;
-    acc[3 * (int64_t)N + k] = 0.0;
 }
 
-__global__ void finish_kernel(const double *acc, const int *perm, int N, float *ax, float *ay, float *az,
+// Bounding box {x_lo, x_hi, y_lo, y_hi, z_lo, z_hi, h_max, 0} of the records
+// 64b .. 64b+63 (those below N); one wave per box.
+__global__ void box_kernel(const SrcRec *rec, int N, double *box) {
+    const int b = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t k = (int64_t)b * 64 + (threadIdx.x & 63);
+    if ((int64_t)b * 64 >= N) return;  // whole wave leaves together
+    double v[7];
+    if (k < N) {
+        const SrcRec r = rec[k];
+        v[0] = r.x;
+        v[1] = -r.x;
+        v[2] = r.y;
+        v[3] = -r.y;
+        v[4] = r.z;
+        v[5] = -r.z;
+        v[6] = (double)r.h;
+    } else {
+        for (int c = 0; c < 6; ++c) v[c] = HUGE_VAL;  // neutral for the minima
+        v[6] = 0.0;
+    }
+    // minima of (x, -x, y, -y, z, -z), maximum of h, over the wave
+    for (int off = 32; off >= 1; off >>= 1) {
+        for (int c = 0; c < 6; ++c) v[c] = fmin(v[c], __shfl_xor(v[c], off));
+        v[6] = fmax(v[6], __shfl_xor(v[6], off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        double *o = box + (int64_t)b * kBox;
+        o[0] = v[0];
+        o[1] = -v[1];
+        o[2] = v[2];
+        o[3] = -v[3];
+        o[4] = v[4];
+        o[5] = -v[5];
+        o[6] = v[6];
+        o[7] = 0.0;
+    }
+}
+
+__global__ void finish_kernel(const double *sum, int P, const int *perm, int N, float *ax, float *ay, float *az,
                               float *pot) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < P; ++q)
+        for (int c = 0; c < 4; ++c) s[c] += sum[((int64_t)q * 4 + c) * N + k];
     const int p = perm[k];
     // attraction: a = -sum m_j S (x_i - x_j), potential = -sum m_j / r
-    ax[p] = (float)(-acc[k]);
-    ay[p] = (float)(-acc[N + k]);
-    az[p] = (float)(-acc[2 * (int64_t)N + k]);
-    if (pot) pot[p] = (float)(-acc[3 * (int64_t)N + k]);
+    ax[p] = (float)(-s[0]);
+    ay[p] = (float)(-s[1]);
+    az[p] = (float)(-s[2]);
+    if (pot) pot[p] = (float)(-s[3]);
 }
 
 template <int kR>
@@ -111,26 +169,71 @@ struct Owned {
     int t[kR];  // record index, or N for an empty slot
 };
 
-// The sources of one LDS tile against the thread's particles.  REACT: the
-// tile belongs to a partner group, so the reactions are reduced and left in
-// jpart; otherwise (the group against itself) the self pair is skipped.
-// Pair terms are FP32; both sides are summed in FP64 (the records are in
-// spatial order, so a particle's near neighbours arrive together and an
-// FP32 partial would lose their cancellation).
-template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT, int kR = particles_per_thread(TORDER)>
-__device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned<kR> &o, const SrcRec *tile, int base,
-                                          int cnt, float hmax, double (*acc)[4], double (*jpart)[kTile][4]) {
+struct WaveBox {
+    double x0, x1, y0, y1, z0, z1, h;
+};
+
+// True when no pair between the wave's particles (box w) and the records of
+// box b needs the softening or the half-period screen: the boxes are apart by
+// more than the sum of their largest softenings (with that sum below L/2, so
+// that no image n != 0 is softened either) and no axial separation comes
+// near L/2.  Evaluated alike by every lane.
+__device__ __forceinline__ bool far_boxes(const PairwiseArgs &a, const WaveBox &w, const double *b) {
+    const double hs = w.h + b[6];
+    if (hs > a.far_h) return false;
+    const double gx = fmax(0.0, fmax(w.x0 - b[1], b[0] - w.x1));
+    const double gy = fmax(0.0, fmax(w.y0 - b[3], b[2] - w.y1));
+    // axial separations t = z_i - z_j lie in [tl, th], inside (-L, L)
+    const double tl = w.z0 - b[5], th = w.z1 - b[4];
+    double gz;
+    if (ceil(tl * a.invL) <= floor(th * a.invL)) {
+        gz = 0.0;  // a multiple of L inside: some pair may be axially aligned
+    } else {
+        const double el = fabs(tl - a.L * rint(tl * a.invL)), eh = fabs(th - a.L * rint(th * a.invL));
+        gz = fmin(el, eh);
+    }
+    // no separation within 1e-5 L of a half period (the screen is 5e-7 L)
+    const double m = 1e-5 * a.L;
+    if (ceil((tl - m) * a.invL - 0.5) <= floor((th + m) * a.invL - 0.5)) return false;
+    return gx * gx + gy * gy + gz * gz > hs * hs * (1.0 + 1e-4) + 1e-300;
+}
+
+// LDS of a workgroup: the tile's sources (SoA) and the waves' reaction slots.
+struct Stage {
+    double x[kTile], y[kTile], z[kTile];
+    float m[kTile], h[kTile];
+    double r[kWaves][4][kTile];
+};
+
+// One wave's rotation over sub-tile s: 64 steps, lane l taking source
+// (l + step) mod 64.  REACT: the sources belong to another group; their
+// reactions (in the owned sums' orientation, dx = x_i - x_j) are summed in the
+// wave's LDS slots.  Otherwise (the group against itself) the self pair is
+// skipped.  FAST: the sub-tile is far from the wave's particles (far_boxes),
+// so neither the softening nor the half-period screen can trigger.  Pair
+// terms are FP32, sums FP64 (the records are in spatial order, so a
+// particle's near neighbours arrive together and an FP32 partial would lose
+// their cancellation).
+template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT, bool FAST, int kR>
+__device__ __forceinline__ void sub_pass(const PairwiseArgs &a, const Owned<kR> &o, Stage &st, int s, int base,
+                                         float hmax, double (*acc)[4]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float thr2[kR];
     bool wide[kR];
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-        const float hb = o.h[r] + hmax;  // >= h_i + h_j for every source of the tile
+        const float hb = o.h[r] + hmax;  // >= h_i + h_j for every source of the sub-tile
         thr2[r] = hb * hb;
         wide[r] = hb > (float)a.halfL;
     }
-    for (int si = 0; si < cnt; ++si) {
-        const SrcRec src = tile[si];
+    for (int step = 0; step < kSub; ++step) {
+        const int k = (s << 6) | ((lane + step) & 63);
+        SrcRec src;
+        src.x = st.x[k];
+        src.y = st.y[k];
+        src.z = st.z[k];
+        src.m = st.m[k];
+        src.h = st.h[k];
         double dx64[kR], dy64[kR];
         float S[kR], Fz[kR], P[kR], dr[kR];
         bool tie[kR];
@@ -144,44 +247,49 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned<kR>
             dr[r] = d;
             P[r] = 0.f;
             pair_fast<NIMG, POT>(dx, dy, d, a.c, S[r], Fz[r], P[r]);
-            const float r2_0 = __builtin_fmaf(d, d, __builtin_fmaf(dx, dx, dy * dy));
-            const float hij = o.h[r] + src.h;
-            if ((wide[r] || r2_0 < thr2[r]) && (r2_0 < hij * hij || hij > (float)a.halfL)) soft |= 1u << r;
-            tie[r] = REACT && __builtin_fabsf(d) >= a.tie32;
-        }
-        while (soft) {
-            // rare and divergent: one pair per lane and pass, operands picked
-            // by selects so that the spline code exists once
-            const int rr = __builtin_ctz(soft);
-            soft &= soft - 1;
-            double xr = o.x[0], yr = o.y[0], zr = o.z[0];
-            float hr = o.h[0];
-            int tr = o.t[0];
-#pragma unroll
-            for (int k = 1; k < kR; ++k)
-                if (rr == k) {
-                    xr = o.x[k];
-                    yr = o.y[k];
-                    zr = o.z[k];
-                    hr = o.h[k];
-                    tr = o.t[k];
-                }
-            float gS = 0.f, gF = 0.f, gP = 0.f;
-            if (REACT || base + si != tr) {
-                double gs, gf, gp;
-                pair_spline_f64(xr - src.x, yr - src.y, min_image(zr - src.z, a.L, a.invL),
-                                (double)hr + (double)src.h, a.L, (NIMG >= 0) ? NIMG : a.c.n_img, gs, gf, gp);
-                gS = (float)gs;
-                gF = (float)gf;
-                gP = (float)gp;
+            tie[r] = false;
+            if (!FAST) {
+                const float r2_0 = __builtin_fmaf(d, d, __builtin_fmaf(dx, dx, dy * dy));
+                const float hij = o.h[r] + src.h;
+                if ((wide[r] || r2_0 < thr2[r]) && (r2_0 < hij * hij || hij > (float)a.halfL)) soft |= 1u << r;
+                tie[r] = REACT && __builtin_fabsf(d) >= a.tie32;
             }
+        }
+        if (!FAST) {
+            while (soft) {
+                // rare and divergent: one pair per lane and pass, operands
+                // picked by selects so that the spline code exists once
+                const int rr = __builtin_ctz(soft);
+                soft &= soft - 1;
+                double xr = o.x[0], yr = o.y[0], zr = o.z[0];
+                float hr = o.h[0];
+                int tr = o.t[0];
 #pragma unroll
-            for (int k = 0; k < kR; ++k)
-                if (rr == k) {
-                    S[k] = gS;
-                    Fz[k] = gF;
-                    P[k] = gP;
+                for (int q = 1; q < kR; ++q)
+                    if (rr == q) {
+                        xr = o.x[q];
+                        yr = o.y[q];
+                        zr = o.z[q];
+                        hr = o.h[q];
+                        tr = o.t[q];
+                    }
+                float gS = 0.f, gF = 0.f, gP = 0.f;
+                if (REACT || base + k != tr) {
+                    double gs, gf, gp;
+                    pair_spline_f64(xr - src.x, yr - src.y, min_image(zr - src.z, a.L, a.invL),
+                                    (double)hr + (double)src.h, a.L, (NIMG >= 0) ? NIMG : a.c.n_img, gs, gf, gp);
+                    gS = (float)gs;
+                    gF = (float)gf;
+                    gP = (float)gp;
                 }
+#pragma unroll
+                for (int q = 0; q < kR; ++q)
+                    if (rr == q) {
+                        S[q] = gS;
+                        Fz[q] = gF;
+                        P[q] = gP;
+                    }
+            }
         }
         if (TORDER > 0) {
             // far images from the table (Sect. 2.2, eq. S1R2EwaldCorrectionTable):
@@ -193,7 +301,7 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned<kR>
                 const float rho = __builtin_sqrtf(__builtin_fmaf(dx, dx, dy * dy));
                 const float rr = rho * a.invLf;
                 const float delta = __builtin_fabsf(dr[r]) * a.invLf;
-                const bool self = !REACT && base + si == o.t[r];
+                const bool self = !REACT && base + k == o.t[r];
                 const bool inside = (rr <= a.tv.r_max) && !self;
                 float tz, tr;
                 lookup<(TORDER > 0 ? TORDER : 1)>(a.tv, delta, inside ? rr : 0.f, tz, tr);
@@ -230,6 +338,13 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned<kR>
         }
         const double ms = (double)src.m;
         double jx = 0.0, jy = 0.0, jz = 0.0, jp = 0.0;
+        if (REACT && step > 0) {
+            // the slot as the previous lane left it
+            jx = st.r[wave][0][k];
+            jy = st.r[wave][1][k];
+            jz = st.r[wave][2][k];
+            if (POT) jp = st.r[wave][3][k];
+        }
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
             const double S64 = (double)S[r], Fz64 = (double)Fz[r];
@@ -242,7 +357,7 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned<kR>
                 // the source sees -dx, -dy and -d, except where |d| = L/2 up to
                 // rounding and its own minimum image has the sign of d
                 double fz = Fz64;
-                if (tie[r]) {
+                if (!FAST && tie[r]) {
                     const double d64 = min_image(o.z[r] - src.z, a.L, a.invL);
                     if (__builtin_fabs(__builtin_fabs(d64) - a.halfL) <= a.tie) {
                         const double dji = min_image(src.z - o.z[r], a.L, a.invL);
@@ -257,167 +372,239 @@ __device__ __forceinline__ void tile_pass(const PairwiseArgs &a, const Owned<kR>
             }
         }
         if (REACT) {
-            // reduce-scatter over the wave: lanes 16q..16q+15 end with
-            // component q (x, y, z, potential) summed over all 64 lanes
-            const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
-            double k0 = b5 ? jz : jx, k1 = b5 ? jp : jy;
-            k0 += __shfl_xor(b5 ? jx : jz, 32);
-            k1 += __shfl_xor(b5 ? jy : jp, 32);
-            double kp = b4 ? k1 : k0;
-            kp += __shfl_xor(b4 ? k0 : k1, 16);
-            kp += __shfl_xor(kp, 8);
-            kp += __shfl_xor(kp, 4);
-            kp += __shfl_xor(kp, 2);
-            kp += __shfl_xor(kp, 1);
-            if ((lane & 15) == 0) jpart[wave][si][lane >> 4] = kp;
+            st.r[wave][0][k] = jx;
+            st.r[wave][1][k] = jy;
+            st.r[wave][2][k] = jz;
+            if (POT) st.r[wave][3][k] = jp;
         }
     }
 }
 
-template <int NIMG, bool POT, int TORDER, bool COMPLETE>
+// One meeting (REACT: group a against chunk q of group b in tournament round
+// a.round) or one self meeting (group a against chunk q of itself).
+template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT>
 __global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseArgs a) {
     constexpr int kR = particles_per_thread(TORDER);
     constexpr int kGroup = kThreads * kR;  // particles per group
-    __shared__ SrcRec tile[kTile];
-    __shared__ float wave_hmax[kThreads / 64];
-    __shared__ double jpart[kThreads / 64][kTile][4];
-    const int tid = threadIdx.x;
-    const int g = blockIdx.x / a.P, q = blockIdx.x % a.P;
+    __shared__ Stage st;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int meet = blockIdx.x / a.P, q = blockIdx.x % a.P;
+    int ga = meet, gb = meet;
+    if (REACT) {
+        const int M = a.Gp - 1;
+        if (meet == 0) {
+            ga = M;
+            gb = a.round;
+        } else {
+            ga = (a.round + meet) % M;
+            gb = (a.round - meet + M) % M;
+        }
+        if (ga >= a.G || gb >= a.G) return;  // the empty group of an odd count (whole workgroup)
+    }
 
+    // the wave's particles: records ga*kGroup + wave*64*kR + r*64 + lane;
+    // empty slots copy the group's first record with no mass (they sit where
+    // a particle is, so every pair distance stays that of a real pair)
     Owned<kR> o;
+    const int64_t g0 = (int64_t)ga * kGroup;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-        const int64_t t64 = (int64_t)g * kGroup + r * kThreads + tid;
-        const int t = t64 < a.N ? (int)t64 : a.N;  // a.N marks an empty slot
-        o.t[r] = t;
-        if (t < a.N) {
-            const SrcRec rr = a.rec[t];
-            o.x[r] = rr.x;
-            o.y[r] = rr.y;
-            o.z[r] = rr.z;
-            o.h[r] = rr.h;
-            o.m[r] = rr.m;
-        } else {
-            // an empty slot far from every particle, with no mass: its
-            // reactions vanish and its own sums are never written
-            o.x[r] = 1e18;
-            o.y[r] = 0.0;
-            o.z[r] = 0.0;
-            o.h[r] = 0.f;
-            o.m[r] = 0.f;
-        }
+        const int64_t t64 = g0 + (int64_t)wave * 64 * kR + r * 64 + lane;
+        const bool real = t64 < a.N;
+        const SrcRec rr = a.rec[real ? t64 : g0];
+        o.t[r] = real ? (int)t64 : a.N;
+        o.x[r] = rr.x;
+        o.y[r] = rr.y;
+        o.z[r] = rr.z;
+        o.h[r] = rr.h;
+        o.m[r] = real ? rr.m : 0.f;
     }
+    // the wave's bounding box (every lane ends with it)
+    WaveBox wb;
+    {
+        double v[7] = {o.x[0], -o.x[0], o.y[0], -o.y[0], o.z[0], -o.z[0], (double)o.h[0]};
+#pragma unroll
+        for (int r = 1; r < kR; ++r) {
+            v[0] = fmin(v[0], o.x[r]);
+            v[1] = fmin(v[1], -o.x[r]);
+            v[2] = fmin(v[2], o.y[r]);
+            v[3] = fmin(v[3], -o.y[r]);
+            v[4] = fmin(v[4], o.z[r]);
+            v[5] = fmin(v[5], -o.z[r]);
+            v[6] = fmax(v[6], (double)o.h[r]);
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            for (int c = 0; c < 6; ++c) v[c] = fmin(v[c], __shfl_xor(v[c], off));
+            v[6] = fmax(v[6], __shfl_xor(v[6], off));
+        }
+        wb.x0 = v[0];
+        wb.x1 = -v[1];
+        wb.y0 = v[2];
+        wb.y1 = -v[3];
+        wb.z0 = v[4];
+        wb.z1 = -v[5];
+        wb.h = v[6];
+    }
+
     double acc[kR][4];
 #pragma unroll
     for (int r = 0; r < kR; ++r)
-        for (int k = 0; k < 4; ++k) acc[r][k] = 0.0;
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
 
-    const int half = a.G / 2;
-    const int K = (a.G & 1) ? half : half - 1 + (g < half ? 1 : 0);
-    const int U = K + 1;  // the group itself and its K partners
-    const int u0 = (int)((int64_t)q * U / a.P), u1 = (int)((int64_t)(q + 1) * U / a.P);
-    for (int u = u0; u < u1; ++u) {
-        const int h = (g + u) % a.G;
-        // index arithmetic that stays below N (no int overflow near 2^31)
-        const int gbase = h * kGroup, gend = gbase + min(kGroup, a.N - gbase);
-        for (int base = gbase, cnt = 0; base < gend; base += cnt) {
-            cnt = min(kTile, gend - base);
-            float hj = 0.f;
-            if (tid < cnt) {
-                const SrcRec rr = a.rec[base + tid];
-                hj = rr.h;
-                tile[tid] = rr;
-            }
-            for (int off = 32; off >= 1; off >>= 1) hj = fmaxf(hj, __shfl_xor(hj, off));
-            if ((tid & 63) == 0) wave_hmax[tid >> 6] = hj;
-            __syncthreads();
-            float hmax = wave_hmax[0];
-            for (int w = 1; w < kThreads / 64; ++w) hmax = fmaxf(hmax, wave_hmax[w]);
-            if (u == 0) {
-                tile_pass<NIMG, POT, TORDER, COMPLETE, false>(a, o, tile, base, cnt, hmax, acc, jpart);
-                __syncthreads();
-            } else {
-                tile_pass<NIMG, POT, TORDER, COMPLETE, true>(a, o, tile, base, cnt, hmax, acc, jpart);
-                __syncthreads();
-                if (tid < cnt) {
-                    // reaction on source base + tid, in the owned sums' sign convention
-                    const int64_t jj = base + tid;
-                    double v[4];
+    const int64_t cb64 = (int64_t)gb * kGroup + (int64_t)q * a.chunk;
+    const int cbeg = (int)min(cb64, (int64_t)a.N), cend = (int)min(cb64 + a.chunk, (int64_t)a.N);
+    for (int base = cbeg; base < cend; base += kTile) {
+        const int cnt = min(kTile, cend - base);
+        const int nsub = (cnt + kSub - 1) / kSub;
+        // stage the tile; a partly filled sub-tile is padded with massless
+        // copies of its first record (inside its box)
+        if (tid < nsub * kSub) {
+            const int first = base + (tid & ~(kSub - 1));
+            const bool real = tid < cnt;
+            const SrcRec rr = a.rec[real ? base + tid : first];
+            st.x[tid] = rr.x;
+            st.y[tid] = rr.y;
+            st.z[tid] = rr.z;
+            st.m[tid] = real ? rr.m : 0.f;
+            st.h[tid] = rr.h;
+        }
+        __syncthreads();
+        for (int s = 0; s < nsub; ++s) {
+            const double *b = a.box + (int64_t)((base >> 6) + s) * kBox;  // base is a multiple of 64
+            const bool fast = far_boxes(a, wb, b);
+            const float hmax = (float)b[6];
+            if (__builtin_amdgcn_readfirstlane((int)fast))
+                sub_pass<NIMG, POT, TORDER, COMPLETE, REACT, true>(a, o, st, s, base, hmax, acc);
+            else
+                sub_pass<NIMG, POT, TORDER, COMPLETE, REACT, false>(a, o, st, s, base, hmax, acc);
+        }
+        __syncthreads();
+        if (REACT && tid < cnt) {
+            // reaction on source base + tid, in the owned sums' orientation:
+            // the 4 waves' slots in order, added to slot 0 of the source
+            const int64_t jj = base + tid;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        v[k] = (jpart[0][tid][k] + jpart[1][tid][k]) + (jpart[2][tid][k] + jpart[3][tid][k]);
-                    unsafeAtomicAdd(a.acc + jj, -v[0]);
-                    unsafeAtomicAdd(a.acc + a.N + jj, -v[1]);
-                    unsafeAtomicAdd(a.acc + 2 * (int64_t)a.N + jj, -v[2]);
-                    if (POT) unsafeAtomicAdd(a.acc + 3 * (int64_t)a.N + jj, v[3]);
-                }
+            for (int c = 0; c < 4; ++c) {
+                if (c == 3 && !POT) continue;
+                const double v = (st.r[0][c][tid] + st.r[1][c][tid]) + (st.r[2][c][tid] + st.r[3][c][tid]);
+                double *p = a.sum + (int64_t)c * a.N + jj;
+                *p = (c == 3) ? *p + v : *p - v;
             }
         }
+        // the next tile's staging overwrites only the source arrays, which
+        // every wave has finished reading at the barrier above; the slots are
+        // written again only after the next barrier
     }
+    // the group's own sums from this chunk: slot q
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         if (o.t[r] < a.N) {
-            unsafeAtomicAdd(a.acc + o.t[r], acc[r][0]);
-            unsafeAtomicAdd(a.acc + a.N + o.t[r], acc[r][1]);
-            unsafeAtomicAdd(a.acc + 2 * (int64_t)a.N + o.t[r], acc[r][2]);
-            if (POT) unsafeAtomicAdd(a.acc + 3 * (int64_t)a.N + o.t[r], acc[r][3]);
+            double *p = a.sum + (int64_t)q * 4 * a.N + o.t[r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c == 3 && !POT) continue;
+                if (REACT)
+                    p[(int64_t)c * a.N] += acc[r][c];
+                else
+                    p[(int64_t)c * a.N] = acc[r][c];  // the self meeting initialises every slot
+            }
         }
     }
 }
 
 template <int NIMG, bool POT, int TORDER, bool COMPLETE>
-hipError_t launch_t(const PairwiseArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL((forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE>), dim3(a.G * a.P), dim3(kThreads), 0,
-                       stream, a);
-    return hipGetLastError();
-}
-
-template <bool POT>
-hipError_t launch_nimg(const PairwiseArgs &a, hipStream_t stream) {
-    switch (a.c.n_img) {
-        case 0: return launch_t<0, POT, 0, false>(a, stream);
-        case 1: return launch_t<1, POT, 0, false>(a, stream);
-        case 2: return launch_t<2, POT, 0, false>(a, stream);
-        case 4: return launch_t<4, POT, 0, false>(a, stream);
-        case 8: return launch_t<8, POT, 0, false>(a, stream);
-        default: return launch_t<-1, POT, 0, false>(a, stream);
+struct Launcher {
+    // workgroups of the meeting kernel resident per CU
+    static int blocks_per_cu() {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE, true>,
+                                                         kThreads, 0) != hipSuccess)
+            n = 1;
+        return std::max(1, n);
     }
+    static hipError_t run(PairwiseArgs a, hipStream_t stream) {
+        hipLaunchKernelGGL((forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE, false>), dim3(a.G * a.P),
+                           dim3(kThreads), 0, stream, a);
+        hipError_t e = hipGetLastError();
+        for (int r = 0; e == hipSuccess && r + 1 < a.Gp; ++r) {
+            a.round = r;
+            hipLaunchKernelGGL((forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE, true>), dim3(a.Gp / 2 * a.P),
+                               dim3(kThreads), 0, stream, a);
+            e = hipGetLastError();
+        }
+        return e;
+    }
+};
+
+// Calls f(Launcher<...>{}) for the kernel instance of (n_img, pot, table order, complete).
+template <class F>
+auto dispatch(int n_img, bool pot, int order, bool complete, F &&f) {
+    if (order == 0) {
+        if (pot) {
+            switch (n_img) {
+                case 0: return f(Launcher<0, true, 0, false>{});
+                case 1: return f(Launcher<1, true, 0, false>{});
+                case 2: return f(Launcher<2, true, 0, false>{});
+                case 4: return f(Launcher<4, true, 0, false>{});
+                case 8: return f(Launcher<8, true, 0, false>{});
+                default: return f(Launcher<-1, true, 0, false>{});
+            }
+        }
+        switch (n_img) {
+            case 0: return f(Launcher<0, false, 0, false>{});
+            case 1: return f(Launcher<1, false, 0, false>{});
+            case 2: return f(Launcher<2, false, 0, false>{});
+            case 4: return f(Launcher<4, false, 0, false>{});
+            case 8: return f(Launcher<8, false, 0, false>{});
+            default: return f(Launcher<-1, false, 0, false>{});
+        }
+    }
+    if (order == 1) {
+        if (pot) return complete ? f(Launcher<1, true, 1, true>{}) : f(Launcher<1, true, 1, false>{});
+        return complete ? f(Launcher<1, false, 1, true>{}) : f(Launcher<1, false, 1, false>{});
+    }
+    if (pot) return complete ? f(Launcher<1, true, 2, true>{}) : f(Launcher<1, true, 2, false>{});
+    return complete ? f(Launcher<1, false, 2, true>{}) : f(Launcher<1, false, 2, false>{});
 }
 
-template <bool POT>
-hipError_t launch_table(const PairwiseArgs &a, int order, bool complete, hipStream_t stream) {
-    if (order == 1)
-        return complete ? launch_t<1, POT, 1, true>(a, stream) : launch_t<1, POT, 1, false>(a, stream);
-    return complete ? launch_t<1, POT, 2, true>(a, stream) : launch_t<1, POT, 2, false>(a, stream);
+// Workgroups per meeting: the smallest P (chunks of kGroup/P sources, at
+// least 64) whose launches fill the resident workgroup slots to within 10%
+// of the best choice.  `resident` is the number of workgroups the device
+// holds at once for the meeting kernel.
+int choose_P(int Gp, int kGroup, int resident) {
+    const int64_t meetings = Gp / 2;
+    double eff[8] = {0};
+    int cand[8], nc = 0;
+    double best = 0.0;
+    for (int P = 1; P <= kGroup / kSub && nc < 8; P *= 2) cand[nc++] = P;
+    for (int i = 0; i < nc; ++i) {
+        const int64_t W = meetings * cand[i];
+        const int64_t waves = (W + resident - 1) / resident;
+        eff[i] = (double)W / (double)(waves * resident);
+        best = std::max(best, eff[i]);
+    }
+    for (int i = 0; i < nc; ++i)
+        if (eff[i] >= 0.9 * best) return cand[i];
+    return 1;
 }
 
 }  // namespace
 
 // Launches the pairwise path for all N particles: exact images |n| <= n_img,
 // or (table non-null) images |n| <= 1 plus the table's far images with CIC
-// (order 1) or TSC (order 2) interpolation.  Arguments already validated.  Scratch (spatial order, records, FP64 sums) is
-// stream-ordered.
+// (order 1) or TSC (order 2) interpolation.  Arguments already validated.
+// Scratch (spatial order, records, boxes, FP64 sums) is stream-ordered.
 int launch_forces_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
                            int n_img, const steps_cyl_table *table, int order, float *out_acc, float *out_pot,
                            hipStream_t stream) {
-    void *order_scratch = nullptr;
-    const int *perm = nullptr;
-    int rc = order_targets(pos, N, L, nullptr, N, stream, &order_scratch, &perm);
-    if (rc) return rc;
-    void *buf = nullptr;
-    const size_t bytes = (size_t)N * (sizeof(SrcRec) + 4 * sizeof(double));
-    hipError_t e = hipMallocAsync(&buf, bytes, stream);
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(order_scratch, stream);
-        return fail(STEPS_ENOMEM, "pairwise scratch (%zu bytes)", bytes);
-    }
+    const int kR = particles_per_thread(table ? 1 : 0);
+    const int group = kThreads * kR;
     PairwiseArgs a;
-    a.rec = (const SrcRec *)buf;
-    a.acc = (double *)((char *)buf + (size_t)N * sizeof(SrcRec));
     a.L = L;
     a.invL = 1.0 / L;
     a.halfL = 0.5 * L;
     a.tie = 1e-12 * L;
+    a.far_h = 0.49 * L;
     a.tie32 = (float)(0.5 * L * (1.0 - 1e-6));
     a.c.Lf = (float)L;
     a.c.L2f = (float)(L * L);
@@ -427,25 +614,45 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
     a.invL2f = (float)(1.0 / (L * L));
     if (table) a.tv = table_view(table);
     a.N = (int)N;
-    const int group = kThreads * particles_per_thread(table ? 1 : 0);
     a.G = (int)((N + group - 1) / group);
-    // enough workgroups to fill the chip: about 2048, never more than the
-    // units of a group's list
-    const int units = a.G / 2 + 1;
-    a.P = std::max(1, std::min(units, (2048 + a.G - 1) / a.G));
+    a.Gp = a.G + (a.G & 1);
+    a.round = 0;
+    const int ord = table ? order : 0;
+    const bool complete = table && table->complete != 0;
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_status(e, "device attributes");
+    const int per_cu = dispatch(a.c.n_img, out_pot != nullptr, ord, complete, [](auto l) { return l.blocks_per_cu(); });
+    a.P = choose_P(a.Gp, group, per_cu * std::max(1, cus));
+    a.chunk = group / a.P;
+
+    void *order_scratch = nullptr;
+    const int *perm = nullptr;
+    int rc = order_targets(pos, N, L, nullptr, N, stream, &order_scratch, &perm);
+    if (rc) return rc;
+    void *buf = nullptr;
+    const int64_t nbox = (N + 63) / 64;
+    const size_t bytes = (size_t)N * sizeof(SrcRec) + (size_t)nbox * kBox * sizeof(double) +
+                         (size_t)a.P * 4 * N * sizeof(double);
+    e = hipMallocAsync(&buf, bytes, stream);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(order_scratch, stream);
+        return fail(STEPS_ENOMEM, "pairwise scratch (%zu bytes)", bytes);
+    }
+    a.rec = (const SrcRec *)buf;
+    a.box = (const double *)((char *)buf + (size_t)N * sizeof(SrcRec));
+    a.sum = (double *)((char *)buf + (size_t)N * sizeof(SrcRec) + (size_t)nbox * kBox * sizeof(double));
     const int nb = (int)((N + 255) / 256);
     hipLaunchKernelGGL(stage_kernel, dim3(nb), dim3(256), 0, stream, pos, mass, eps, (int)N, L, perm,
-                       (SrcRec *)buf, a.acc);
+                       (SrcRec *)buf);
+    hipLaunchKernelGGL(box_kernel, dim3((unsigned)((nbox + 3) / 4)), dim3(256), 0, stream, a.rec, (int)N,
+                       (double *)a.box);
     e = hipGetLastError();
+    if (e == hipSuccess)
+        e = dispatch(a.c.n_img, out_pot != nullptr, ord, complete, [&](auto l) { return l.run(a, stream); });
     if (e == hipSuccess) {
-        if (table)
-            e = out_pot ? launch_table<true>(a, order, table->complete != 0, stream)
-                        : launch_table<false>(a, order, table->complete != 0, stream);
-        else
-            e = out_pot ? launch_nimg<true>(a, stream) : launch_nimg<false>(a, stream);
-    }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(finish_kernel, dim3(nb), dim3(256), 0, stream, a.acc, perm, (int)N, out_acc,
+        hipLaunchKernelGGL(finish_kernel, dim3(nb), dim3(256), 0, stream, a.sum, a.P, perm, (int)N, out_acc,
                            out_acc + N, out_acc + 2 * N, out_pot);
         e = hipGetLastError();
     }

@@ -54,6 +54,29 @@ def test_f64_reference_with_1024_images_matches_oracle(sc):
     assert np.abs(pot.cpu().numpy() - p_ref).max() < 1e-11 * np.abs(p_ref).max()
 
 
+@pytest.mark.timeout(900)
+def test_f64_reference_with_1024_images_matches_oracle_at_full_size(sc):
+    # The truth of the learned and table accuracy figures at N = 2^20 and of
+    # every force check of the time integration is this kernel; pin it there
+    # to the CPU oracle on 64 targets (1.4e11 FP64 image terms on the host).
+    # Both sides sum the same 2^20 x 2049 terms in FP64 in different orders:
+    # with a random-walk rounding of sqrt(2^31) u = 5e-12 of the sum of
+    # |terms|, and that sum at most ~600 times |a| on this load, 1e-9 bounds
+    # the difference.
+    p = synth.cylinder_load(1 << 20, seed=0)
+    pos, m, e = to_dev(p)
+    t = synth.target_sample(p.N, 64, seed=21)
+    print("[case] f64 |n|<=1024 N=2^20, 64 targets", flush=True)
+    acc, pot = sc.steps_cyl_forces_f64(pos, m, e, p.L, 1024, targets=torch.from_numpy(t).cuda())
+    torch.cuda.synchronize()
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 1024, targets=t)
+    err = rel(acc, a_ref)
+    perr = np.abs(pot.cpu().numpy() - p_ref) / np.abs(p_ref)
+    print(f"f64 reference vs oracle at 2^20: max {err.max():.2e}, potential {perr.max():.2e}")
+    assert err.max() < 1e-9
+    assert perr.max() < 1e-9
+
+
 def test_trained_correction_accuracy_and_gain(sc):
     assert os.path.exists(NET), NET
     net = sc.Mlp.load(NET)

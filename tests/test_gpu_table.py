@@ -143,9 +143,12 @@ def test_pairwise_table_path_matches_per_target_path_and_oracle(sc, order, compl
     pos, m, e = to_dev(p)
     print(f"[case] pairwise table order={order} complete={complete} rho_max={rho_max}", flush=True)
     full, fpot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order)
+    # the pairwise schedule is fixed (no atomics): a second call is bitwise equal
+    full2, fpot2 = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order)
     every = torch.arange(p.N, dtype=torch.int64, device=pos.device)
     one, opot = sc.steps_cyl_forces_table(pos, m, e, p.L, t, order=order, targets=every)
     torch.cuda.synchronize()
+    assert torch.equal(full, full2) and torch.equal(fpot, fpot2)
     # the two paths sum the same FP32 pair terms in FP64 and in compensated
     # FP32: they differ by the per-target path's rounding (2.6e-6 seen)
     assert rel(full, one).max() <= 1e-5

@@ -97,6 +97,92 @@ def test_gradient_matches_library_autograd():
     np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-14)
 
 
+def _bf16_torch(x):
+    return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def test_bf16_forward_straight_through_gradient_matches_library_autograd():
+    # the BF16 forward with every rounding passed straight through in the
+    # backward pass (round_dz=False): library autograd on the rounded
+    # weights, with x + (bf16(x) - x).detach() for the rounded activations
+    rng = np.random.default_rng(8)
+    p = synth.mlp_init(seed=9, out_gain=1.0).astype(np.float64)
+    F = rng.uniform(-1, 1, (2, 96))
+    T = rng.standard_normal((2, 96)) * 0.4
+    loss, g = mlp.loss_and_grad(p, F, T, bf16=True, round_dz=False)
+    leaves = []
+    for W, b in mlp.unpack(p):
+        Wt = torch.from_numpy(W).requires_grad_(True)
+        bt = torch.from_numpy(b).requires_grad_(True)
+        leaves.append((Wt, bt))
+    h = torch.from_numpy(F).to(torch.float32).to(torch.float64)
+    for k, (Wt, bt) in enumerate(leaves):
+        Wq = Wt + (_bf16_torch(Wt) - Wt).detach()
+        bq = bt + (bt.to(torch.float32).to(torch.float64) - bt).detach()
+        x = h + (_bf16_torch(h) - h).detach() if 1 <= k <= mlp.DEPTH - 1 else h
+        z = Wq @ x + bq[:, None]
+        h = torch.nn.functional.silu(z * math.log(2.0)) / math.log(2.0) if k < mlp.DEPTH else z
+    lt = ((h - torch.from_numpy(T)) ** 2).mean()
+    lt.backward()
+    ref = np.concatenate([np.concatenate([Wt.grad.numpy().ravel(), bt.grad.numpy().ravel()])
+                          for Wt, bt in leaves])
+    assert loss == pytest.approx(lt.item(), rel=1e-12)
+    np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-14)
+
+
+def test_bf16_gradient_rounding_within_its_derived_bound(monkeypatch):
+    # the deployed backward rounds dz of layers 2-4 to BF16; it may differ
+    # from the plain backward of the same forward only by what that rounding
+    # can cause (tests/mlp_bound.py), and the bound must be met closely
+    from mlp_bound import grad_rounding_bound
+    rng = np.random.default_rng(12)
+    p = synth.mlp_init(seed=13, out_gain=1.0).astype(np.float64)
+    F = rng.uniform(-1, 1, (2, 512))
+    T = rng.standard_normal((2, 512)) * 0.4
+    _, g_r = mlp.loss_and_grad(p, F, T, bf16=True)
+    _, g_e = mlp.loss_and_grad(p, F, T, bf16=True, round_dz=False)
+    bound = grad_rounding_bound(p, F, T)
+    diff = np.abs(g_r - g_e)
+    slack = 1e-13 * np.abs(g_e).max()
+    assert np.all(diff <= bound * (1 + 1e-9) + slack)
+    # per layer: the rounding shows wherever it can act, and nowhere else
+    # (layer 5 and the layer-4 bias see no rounded quantity); on the layer
+    # rounded last (W4) the worst case is met to within two orders, below it
+    # the bound compounds absolute values over the units and samples
+    off = 0
+    for name, shape in mlp.param_shapes():
+        n = int(np.prod(shape))
+        d, b = diff[off:off + n], bound[off:off + n]
+        if name in ("b4", "W5", "b5"):
+            assert np.all(d == 0.0) and np.all(b == 0.0), name
+        else:
+            assert d.max() > 0.0, name
+        off += n
+    # one sample: the layer-4 weight gradient is a single product, and its
+    # bound u |dz| |x| is met to within a factor 2; a rounding to 6
+    # significant bits instead of 8 breaks it
+    F1, T1 = F[:, :1], T[:, :1]
+    b1 = grad_rounding_bound(p, F1, T1)
+    _, g1 = mlp.loss_and_grad(p, F1, T1, bf16=True)
+    _, g1e = mlp.loss_and_grad(p, F1, T1, bf16=True, round_dz=False)
+    sizes = [int(np.prod(sh)) for _, sh in mlp.param_shapes()]
+    w4 = [name for name, _ in mlp.param_shapes()].index("W4")
+    sl = slice(sum(sizes[:w4]), sum(sizes[:w4 + 1]))
+    r = np.abs(g1 - g1e)[sl] / np.maximum(b1[sl], 1e-300)
+    assert r.max() <= 1 + 1e-9 and r.max() >= 0.5
+
+    def coarse(x):
+        f = np.asarray(x, dtype=np.float32)
+        u = f.view(np.uint32).astype(np.uint64)
+        u = (u + 0x1FFFF + ((u >> 18) & 1)) & 0xFFFC0000
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    monkeypatch.setattr(mlp, "bf16_round", coarse)
+    _, g_c = mlp.loss_and_grad(p, F1, T1, bf16=True)
+    _, g_ce = mlp.loss_and_grad(p, F1, T1, bf16=True, round_dz=False)
+    monkeypatch.undo()
+    assert np.any(np.abs(g_c - g_ce) > b1 * (1 + 1e-9) + 1e-13 * np.abs(g1e).max())
+
+
 def test_rod_part_of_baseline_matches_quadrature():
     # remove the end corrections: the remaining rod integrals checked by quad
     for d, r in [(0.0, 0.05), (0.31, 0.7), (0.5, 3.0), (0.12, 19.0)]:
