@@ -24,17 +24,25 @@
  *    doubles), mass[N] >= 0 and eps[N] > 0 (FP64; eps_i is the softening
  *    length h_i).  z may lie anywhere; it is wrapped into [0, L) in FP64 as
  *    z - L floor(z/L) before use.  Outputs are caller-owned device arrays.
- *    The library never frees caller memory and allocates nothing per call
- *    except where an entry point says otherwise.
+ *    The library never frees caller memory.
+ *  - Workspace: the force entry points that need device scratch (spatial
+ *    order, staged records, partial sums) come in two forms.  The *_ws form
+ *    takes a caller-owned device workspace (workspace, workspace_bytes) and
+ *    allocates nothing; steps_cyl_forces_workspace() returns the bytes it
+ *    needs on the current device (STEPS_EINVAL if the workspace is smaller).
+ *    Its contents are undefined after the call; calls that share one
+ *    workspace must be ordered on one stream.  The plain form takes the same
+ *    amount as stream-ordered memory (hipMallocAsync on `stream`, released
+ *    with hipFreeAsync on it after the call's launches; STEPS_ENOMEM if it
+ *    cannot be had).  Network, table and tree handles own their memory.
  *  - Target order: with 4096 or more targets, the per-target entry points
  *    (steps_cyl_forces_ex in its per-target modes,
- *    steps_cyl_forces_learned[_ex], steps_cyl_forces_table) first sort the
- *    targets by a 30-bit Morton key of (x, y, z) so that each workgroup holds
- *    neighbours; every output stays at its target's position and every
- *    target's result is bitwise that of the unsorted walk.  The keys live in stream-ordered scratch
- *    (hipMallocAsync on `stream`, about 16 bytes per target plus the radix
- *    sort's temporary storage, released with hipFreeAsync on the same
- *    stream); STEPS_ENOMEM if it cannot be had.
+ *    steps_cyl_forces_learned_ex, steps_cyl_forces_table with a list) first
+ *    sort the targets by a 30-bit Morton key of (x, y, z) so that each
+ *    workgroup holds neighbours; every output stays at its target's position
+ *    and every target's result is bitwise that of the unsorted walk.  The
+ *    keys (about 16 bytes per target plus the radix sort's storage) live in
+ *    the workspace.
  *  - Every call is asynchronous on `stream` (0 = the null stream); results
  *    are valid after the stream is synchronised.  Argument errors are found
  *    on the host before any device work and return a negative status; the
@@ -46,6 +54,7 @@
 #ifndef STEPS_CYL_H
 #define STEPS_CYL_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -70,6 +79,14 @@ typedef enum {
  * point: 2^29, so that the kernels' 32-bit offsets into the SoA arrays
  * (component c of particle i at c*N + i, c <= 3) never overflow. */
 #define STEPS_MAX_N (1LL << 29)
+
+typedef struct steps_cyl_table steps_cyl_table;   /* opaque; owns device memory (see below) */
+
+/* Force paths, for steps_cyl_forces_workspace. */
+#define STEPS_PATH_EXACT   0   /* steps_cyl_forces[_ws], steps_cyl_forces_ex[_ws]          */
+#define STEPS_PATH_LEARNED 1   /* steps_cyl_forces_learned[_ws], _learned_ex[_ws]          */
+#define STEPS_PATH_TABLE   2   /* steps_cyl_forces_table[_ws]                              */
+#define STEPS_PATH_F64     3   /* steps_cyl_forces_f64[_ws]                                */
 
 /* Summation modes of steps_cyl_forces_ex. */
 #define STEPS_SUM_COMPENSATED 0   /* FP32 pairs, Kahan-compensated per-target sums */
@@ -99,16 +116,45 @@ typedef enum {
  * FP64 sums.  Groups of 1024 particles in spatial order meet in a fixed
  * round-robin tournament (one launch per round, no atomics), so repeated
  * calls on one device are bitwise equal.  Total momentum is conserved to the
- * rounding of the sums.  Scratch is stream-ordered (hipMallocAsync on
- * `stream`, released on it): 32 bytes per particle for the records, 32 P
- * bytes per particle for the sums (P in 1..16 workgroups per meeting, chosen
- * to fill the device: 1 at N = 2^20) and 1 byte per particle for boxes, plus
+ * rounding of the sums.  Workspace (stream-ordered here; see
+ * steps_cyl_forces_ws): 32 bytes per particle for the records, 32 P bytes
+ * per particle for the sums (P in 1..16 workgroups per meeting, chosen to
+ * fill the device: 1 at N = 2^20) and 1 byte per particle for boxes, plus
  * the spatial order's 16 bytes per particle and radix-sort storage.  Returns
  * STEPS_OK, or STEPS_EINVAL / STEPS_ENOMEM / STEPS_EHIP.
  */
 int steps_cyl_forces(const double *pos, const double *mass, const double *eps,
                      int64_t N, double L, int n_img,
                      float *out_acc, float *out_pot, hipStream_t stream);
+
+/*
+ * steps_cyl_forces_workspace -- device workspace, in bytes, that the *_ws
+ * form of a force call needs on the current device (no device work).
+ *
+ *   path       STEPS_PATH_EXACT, _LEARNED, _TABLE or _F64 (see above)
+ *   N          particles, 1 <= N <= STEPS_MAX_N
+ *   n_img      image count of an exact or FP64 call (otherwise ignored)
+ *   n_targets  0 for a call with targets NULL (every particle), else the
+ *              length of its target list
+ *   mode       summation mode of an exact or learned call: STEPS_SUM_PAIRWISE
+ *              for steps_cyl_forces_ws and steps_cyl_forces_learned_ws
+ *   table, order  the table and order of a table call (else NULL, 0)
+ *   potential  nonzero if the call passes out_pot
+ *   bytes      receives the size (0 if the call needs none)
+ *
+ * Returns STEPS_OK, STEPS_EINVAL or STEPS_ENODEV.
+ */
+int steps_cyl_forces_workspace(int path, int64_t N, int n_img, int64_t n_targets, int mode,
+                               const steps_cyl_table *table, int order, int potential,
+                               size_t *bytes);
+
+/* steps_cyl_forces with a caller-owned device workspace of workspace_bytes
+ * (at least what steps_cyl_forces_workspace returns for STEPS_PATH_EXACT,
+ * n_targets 0, STEPS_SUM_PAIRWISE); allocates nothing.  Same results, bit
+ * for bit, as steps_cyl_forces on the same device. */
+int steps_cyl_forces_ws(const double *pos, const double *mass, const double *eps,
+                        int64_t N, double L, int n_img, float *out_acc, float *out_pot,
+                        void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
  * steps_cyl_forces_ex -- as steps_cyl_forces, for a subset of targets and a
@@ -133,18 +179,31 @@ int steps_cyl_forces_ex(const double *pos, const double *mass, const double *eps
                         const int64_t *targets, int64_t n_targets, int mode,
                         float *out_acc, float *out_pot, hipStream_t stream);
 
+/* steps_cyl_forces_ex with a caller-owned workspace (STEPS_PATH_EXACT). */
+int steps_cyl_forces_ex_ws(const double *pos, const double *mass, const double *eps,
+                           int64_t N, double L, int n_img,
+                           const int64_t *targets, int64_t n_targets, int mode,
+                           float *out_acc, float *out_pot, void *workspace,
+                           size_t workspace_bytes, hipStream_t stream);
+
 /*
  * steps_cyl_forces_f64 -- the same sum with every operation in FP64 on the
  * GPU (a slow reference for precision studies; same definitions, same
  * arguments as steps_cyl_forces_ex, FP64 outputs).  Sources are split into
- * chunks so that small target sets fill the GPU; the chunk partials live in
- * stream-ordered scratch (hipMallocAsync, released on the stream), the one
- * allocation this entry point makes.
+ * chunks so that small target sets fill the GPU; the chunk partials (32
+ * bytes per target and chunk) live in the workspace.
  */
 int steps_cyl_forces_f64(const double *pos, const double *mass, const double *eps,
                          int64_t N, double L, int n_img,
                          const int64_t *targets, int64_t n_targets,
                          double *out_acc, double *out_pot, hipStream_t stream);
+
+/* steps_cyl_forces_f64 with a caller-owned workspace (STEPS_PATH_F64). */
+int steps_cyl_forces_f64_ws(const double *pos, const double *mass, const double *eps,
+                            int64_t N, double L, int n_img,
+                            const int64_t *targets, int64_t n_targets,
+                            double *out_acc, double *out_pot, void *workspace,
+                            size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Learned far-image correction.
@@ -253,12 +312,20 @@ int steps_cyl_mlp_load(const char *path, steps_cyl_mlp **out);
  * away; h_i + h_j below that is assumed).  The learned pair term is odd in
  * the separation (R_z odd in d, R_rho even), so, as in steps_cyl_forces,
  * every unordered pair is evaluated once and applied to both particles, with
- * FP64 sums, run-to-run agreement to one FP32 rounding step and
- * stream-ordered scratch of about 80 bytes per particle.
+ * FP64 sums: groups of 128 particles meet in the round-robin tournament of
+ * steps_cyl_forces (no atomics; repeated calls are bitwise equal).
+ * Workspace about 80 bytes per particle (records, sums, spatial order).
  */
 int steps_cyl_forces_learned(const double *pos, const double *mass, const double *eps,
                              int64_t N, double L, const steps_cyl_mlp *net,
                              float *out_acc, float *out_pot, hipStream_t stream);
+
+/* steps_cyl_forces_learned with a caller-owned workspace (STEPS_PATH_LEARNED,
+ * n_targets 0, STEPS_SUM_PAIRWISE). */
+int steps_cyl_forces_learned_ws(const double *pos, const double *mass, const double *eps,
+                                int64_t N, double L, const steps_cyl_mlp *net,
+                                float *out_acc, float *out_pot, void *workspace,
+                                size_t workspace_bytes, hipStream_t stream);
 
 /* As steps_cyl_forces_learned for a target subset and summation mode
  * (arguments as steps_cyl_forces_ex): per target (STEPS_SUM_COMPENSATED,
@@ -268,6 +335,14 @@ int steps_cyl_forces_learned_ex(const double *pos, const double *mass, const dou
                                 int64_t N, double L, const steps_cyl_mlp *net,
                                 const int64_t *targets, int64_t n_targets, int mode,
                                 float *out_acc, float *out_pot, hipStream_t stream);
+
+/* steps_cyl_forces_learned_ex with a caller-owned workspace
+ * (STEPS_PATH_LEARNED). */
+int steps_cyl_forces_learned_ex_ws(const double *pos, const double *mass, const double *eps,
+                                   int64_t N, double L, const steps_cyl_mlp *net,
+                                   const int64_t *targets, int64_t n_targets, int mode,
+                                   float *out_acc, float *out_pot, void *workspace,
+                                   size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Tabulated far-image correction (Sect. 2.2, eq. S1R2EwaldCorrectionTable:
@@ -286,7 +361,6 @@ int steps_cyl_forces_learned_ex(const double *pos, const double *mass, const dou
  *                   use the line-mass limit F_rho = -2 G m/(L rho) of the
  *                   complete sum (its modes decay as exp(-2 pi rho/L)).
  * ---------------------------------------------------------------------- */
-typedef struct steps_cyl_table steps_cyl_table;   /* opaque; owns device memory */
 
 #define STEPS_TABLE_MAX_FAR (1 << 24)
 
@@ -332,14 +406,22 @@ int steps_cyl_table_info(const steps_cyl_table *table, int *n_delta, int *n_rho,
  * the |n| <= 1 potential.  The table's far-image term is odd in d along z
  * and even in d across, so the tabulated pair is antisymmetric like the
  * exact one.  targets NULL (every particle a target): each unordered pair is
- * evaluated once and applied to both particles, with the arithmetic, run-to-
- * run reproducibility and stream-ordered scratch of steps_cyl_forces.  An
- * explicit target list: one thread per target with Kahan-compensated FP32
- * sums, bitwise deterministic.  Other arguments as steps_cyl_forces_ex. */
+ * evaluated once and applied to both particles, with the arithmetic, the
+ * fixed schedule (bitwise reproducible) and the workspace of steps_cyl_forces
+ * (groups of 512).  An explicit target list: one thread per target with
+ * Kahan-compensated FP32 sums, bitwise deterministic.  Other arguments as
+ * steps_cyl_forces_ex. */
 int steps_cyl_forces_table(const double *pos, const double *mass, const double *eps,
                            int64_t N, double L, const steps_cyl_table *table, int order,
                            const int64_t *targets, int64_t n_targets,
                            float *out_acc, float *out_pot, hipStream_t stream);
+
+/* steps_cyl_forces_table with a caller-owned workspace (STEPS_PATH_TABLE). */
+int steps_cyl_forces_table_ws(const double *pos, const double *mass, const double *eps,
+                              int64_t N, double L, const steps_cyl_table *table, int order,
+                              const int64_t *targets, int64_t n_targets,
+                              float *out_acc, float *out_pot, void *workspace,
+                              size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Barnes-Hut octree (Sect. 2.4, "Octree": cubic cells, root cell twice the

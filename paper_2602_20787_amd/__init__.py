@@ -14,6 +14,9 @@ import os
 __all__ = [
     "StepsError", "lib", "library_path",
     "steps_cyl_forces", "steps_cyl_forces_ex", "steps_cyl_forces_f64",
+    "steps_cyl_forces_workspace", "steps_cyl_forces_ws", "steps_cyl_forces_ex_ws", "steps_cyl_forces_f64_ws",
+    "steps_cyl_forces_learned_ws", "steps_cyl_forces_learned_ex_ws", "steps_cyl_forces_table_ws",
+    "STEPS_PATH_EXACT", "STEPS_PATH_LEARNED", "STEPS_PATH_TABLE", "STEPS_PATH_F64",
     "steps_cyl_last_error", "steps_cyl_version",
     "STEPS_SUM_COMPENSATED", "STEPS_SUM_PLAIN", "STEPS_SUM_PAIRWISE", "STEPS_MAX_NIMG", "STEPS_MAX_N", "STEPS_MLP_PARAMS",
     "steps_cyl_mlp_create", "steps_cyl_mlp_destroy", "steps_cyl_mlp_get_params",
@@ -47,6 +50,10 @@ STEPS_SUM_PAIRWISE = 2
 STEPS_MAX_NIMG = 4096
 STEPS_MAX_N = 1 << 29
 STEPS_MLP_PARAMS = 12802
+STEPS_PATH_EXACT = 0
+STEPS_PATH_LEARNED = 1
+STEPS_PATH_TABLE = 2
+STEPS_PATH_F64 = 3
 
 
 class StepsError(RuntimeError):
@@ -60,6 +67,7 @@ _VP = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _I32 = ctypes.c_int
 _F64 = ctypes.c_double
+_SZ = ctypes.c_size_t
 
 class TrainCfg(ctypes.Structure):
     """Mirror of steps_cyl_train_cfg."""
@@ -123,6 +131,14 @@ _SIGNATURES = {
     "steps_cyl_tree_info": [_VP, _VP, _VP, _VP],
     "steps_cyl_tree_cells": [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
     "steps_cyl_forces_table": [_VP, _VP, _VP, _I64, _F64, _VP, _I32, _VP, _I64, _VP, _VP, _VP],
+    "steps_cyl_forces_workspace": [_I32, _I64, _I32, _I64, _I32, _VP, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)],
+    "steps_cyl_forces_ws": [_VP, _VP, _VP, _I64, _F64, _I32, _VP, _VP, _VP, _SZ, _VP],
+    "steps_cyl_forces_ex_ws": [_VP, _VP, _VP, _I64, _F64, _I32, _VP, _I64, _I32, _VP, _VP, _VP, _SZ, _VP],
+    "steps_cyl_forces_f64_ws": [_VP, _VP, _VP, _I64, _F64, _I32, _VP, _I64, _VP, _VP, _VP, _SZ, _VP],
+    "steps_cyl_forces_learned_ws": [_VP, _VP, _VP, _I64, _F64, _VP, _VP, _VP, _VP, _SZ, _VP],
+    "steps_cyl_forces_learned_ex_ws": [_VP, _VP, _VP, _I64, _F64, _VP, _VP, _I64, _I32, _VP, _VP, _VP, _SZ,
+                                       _VP],
+    "steps_cyl_forces_table_ws": [_VP, _VP, _VP, _I64, _F64, _VP, _I32, _VP, _I64, _VP, _VP, _VP, _SZ, _VP],
 }
 
 
@@ -194,8 +210,38 @@ def _sources(pos, mass, eps):
             _dev(eps, torch.float64, "eps", N))
 
 
+def _ws_args(workspace):
+    """(device pointer, bytes) of a caller's workspace tensor."""
+    import torch
+    if not isinstance(workspace, torch.Tensor) or workspace.device.type != "cuda":
+        raise TypeError("workspace must be a device (cuda) tensor")
+    if not workspace.is_contiguous():
+        raise ValueError("workspace must be contiguous")
+    return workspace.data_ptr(), workspace.numel() * workspace.element_size()
+
+
+def _call(name, args, stream, workspace):
+    """The C entry point `name` (or its _ws form with the workspace inserted
+    before the stream)."""
+    if workspace is None:
+        _check(getattr(lib(), name)(*args, stream))
+    else:
+        _check(getattr(lib(), name + "_ws")(*args, *_ws_args(workspace), stream))
+
+
+def steps_cyl_forces_workspace(path, N, n_img=0, n_targets=0, mode=STEPS_SUM_PAIRWISE, table=None, order=0,
+                               potential=True):
+    """Bytes of device workspace the _ws form of a force call needs on the
+    current device (n_targets 0: targets None)."""
+    b = ctypes.c_size_t()
+    h = None if table is None else (table.handle if hasattr(table, "handle") else table)
+    _check(lib().steps_cyl_forces_workspace(int(path), int(N), int(n_img), int(n_targets), int(mode), h,
+                                            int(order), 1 if potential else 0, ctypes.byref(b)))
+    return b.value
+
+
 def steps_cyl_forces(pos, mass, eps, L, n_img, out_acc=None, out_pot=None, potential=True,
-                     stream=None):
+                     stream=None, workspace=None):
     """Exact image-sum accelerations (3, N) FP32 and potentials (N,) FP32 of
     all particles (``out_pot`` is None when ``potential`` is False).
     ``pos`` is a (3, N) FP64 device tensor, ``mass``/``eps`` (N,) FP64."""
@@ -207,13 +253,19 @@ def steps_cyl_forces(pos, mass, eps, L, n_img, out_acc=None, out_pot=None, poten
         out_pot = torch.empty((N,), dtype=torch.float32, device=pos.device)
     p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * N)
     p_pot = _dev(out_pot, torch.float32, "out_pot", N) if potential else None
-    _check(lib().steps_cyl_forces(p_pos, p_m, p_e, N, float(L), int(n_img), p_acc, p_pot,
-                                  _stream(stream, pos.device)))
+    _call("steps_cyl_forces", (p_pos, p_m, p_e, N, float(L), int(n_img), p_acc, p_pot),
+          _stream(stream, pos.device), workspace)
     return out_acc, (out_pot if potential else None)
 
 
+def steps_cyl_forces_ws(pos, mass, eps, L, n_img, workspace, **kw):
+    """:func:`steps_cyl_forces` in a caller-owned device workspace (a
+    contiguous device tensor of at least steps_cyl_forces_workspace bytes)."""
+    return steps_cyl_forces(pos, mass, eps, L, n_img, workspace=workspace, **kw)
+
+
 def steps_cyl_forces_ex(pos, mass, eps, L, n_img, targets=None, mode=STEPS_SUM_COMPENSATED,
-                        out_acc=None, out_pot=None, potential=True, stream=None):
+                        out_acc=None, out_pot=None, potential=True, stream=None, workspace=None):
     """As :func:`steps_cyl_forces` for the targets listed in ``targets`` (an
     int64 device tensor, or None for all) with summation ``mode``."""
     import torch
@@ -226,13 +278,17 @@ def steps_cyl_forces_ex(pos, mass, eps, L, n_img, targets=None, mode=STEPS_SUM_C
         out_pot = torch.empty((T,), dtype=torch.float32, device=pos.device)
     p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * T)
     p_pot = _dev(out_pot, torch.float32, "out_pot", T) if potential else None
-    _check(lib().steps_cyl_forces_ex(p_pos, p_m, p_e, N, float(L), int(n_img), p_t, T, int(mode),
-                                     p_acc, p_pot, _stream(stream, pos.device)))
+    _call("steps_cyl_forces_ex", (p_pos, p_m, p_e, N, float(L), int(n_img), p_t, T, int(mode), p_acc, p_pot),
+          _stream(stream, pos.device), workspace)
     return out_acc, (out_pot if potential else None)
 
 
+def steps_cyl_forces_ex_ws(pos, mass, eps, L, n_img, workspace, **kw):
+    return steps_cyl_forces_ex(pos, mass, eps, L, n_img, workspace=workspace, **kw)
+
+
 def steps_cyl_forces_f64(pos, mass, eps, L, n_img, targets=None, out_acc=None, out_pot=None,
-                         potential=True, stream=None):
+                         potential=True, stream=None, workspace=None):
     """FP64 GPU evaluation of the same sum (precision yardstick)."""
     import torch
     N, p_pos, p_m, p_e = _sources(pos, mass, eps)
@@ -244,9 +300,13 @@ def steps_cyl_forces_f64(pos, mass, eps, L, n_img, targets=None, out_acc=None, o
         out_pot = torch.empty((T,), dtype=torch.float64, device=pos.device)
     p_acc = _dev(out_acc, torch.float64, "out_acc", 3 * T)
     p_pot = _dev(out_pot, torch.float64, "out_pot", T) if potential else None
-    _check(lib().steps_cyl_forces_f64(p_pos, p_m, p_e, N, float(L), int(n_img), p_t, T, p_acc,
-                                      p_pot, _stream(stream, pos.device)))
+    _call("steps_cyl_forces_f64", (p_pos, p_m, p_e, N, float(L), int(n_img), p_t, T, p_acc, p_pot),
+          _stream(stream, pos.device), workspace)
     return out_acc, (out_pot if potential else None)
+
+
+def steps_cyl_forces_f64_ws(pos, mass, eps, L, n_img, workspace, **kw):
+    return steps_cyl_forces_f64(pos, mass, eps, L, n_img, workspace=workspace, **kw)
 
 
 # ---------------------------------------------------------------- network
@@ -407,7 +467,7 @@ def _handle(net):
 
 
 def steps_cyl_forces_learned(pos, mass, eps, L, net, out_acc=None, out_pot=None, potential=True,
-                             stream=None):
+                             stream=None, workspace=None):
     """Learned-correction accelerations (3, N) FP32 and near-image
     potentials (N,) FP32 of all particles; ``net`` an :class:`Mlp` or handle."""
     import torch
@@ -418,13 +478,17 @@ def steps_cyl_forces_learned(pos, mass, eps, L, net, out_acc=None, out_pot=None,
         out_pot = torch.empty((N,), dtype=torch.float32, device=pos.device)
     p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * N)
     p_pot = _dev(out_pot, torch.float32, "out_pot", N) if potential else None
-    _check(lib().steps_cyl_forces_learned(p_pos, p_m, p_e, N, float(L), _handle(net), p_acc, p_pot,
-                                          _stream(stream, pos.device)))
+    _call("steps_cyl_forces_learned", (p_pos, p_m, p_e, N, float(L), _handle(net), p_acc, p_pot),
+          _stream(stream, pos.device), workspace)
     return out_acc, (out_pot if potential else None)
 
 
+def steps_cyl_forces_learned_ws(pos, mass, eps, L, net, workspace, **kw):
+    return steps_cyl_forces_learned(pos, mass, eps, L, net, workspace=workspace, **kw)
+
+
 def steps_cyl_forces_learned_ex(pos, mass, eps, L, net, targets=None, mode=STEPS_SUM_COMPENSATED,
-                                out_acc=None, out_pot=None, potential=True, stream=None):
+                                out_acc=None, out_pot=None, potential=True, stream=None, workspace=None):
     import torch
     N, p_pos, p_m, p_e = _sources(pos, mass, eps)
     T = N if targets is None else targets.numel()
@@ -435,9 +499,13 @@ def steps_cyl_forces_learned_ex(pos, mass, eps, L, net, targets=None, mode=STEPS
         out_pot = torch.empty((T,), dtype=torch.float32, device=pos.device)
     p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * T)
     p_pot = _dev(out_pot, torch.float32, "out_pot", T) if potential else None
-    _check(lib().steps_cyl_forces_learned_ex(p_pos, p_m, p_e, N, float(L), _handle(net), p_t, T,
-                                             int(mode), p_acc, p_pot, _stream(stream, pos.device)))
+    _call("steps_cyl_forces_learned_ex", (p_pos, p_m, p_e, N, float(L), _handle(net), p_t, T, int(mode), p_acc,
+                                          p_pot), _stream(stream, pos.device), workspace)
     return out_acc, (out_pot if potential else None)
+
+
+def steps_cyl_forces_learned_ex_ws(pos, mass, eps, L, net, workspace, **kw):
+    return steps_cyl_forces_learned_ex(pos, mass, eps, L, net, workspace=workspace, **kw)
 
 
 # ---------------------------------------------------------------- time integration
@@ -589,7 +657,7 @@ class CorrectionTable:
 
 
 def steps_cyl_forces_table(pos, mass, eps, L, table, order=2, targets=None, out_acc=None,
-                           out_pot=None, potential=True, stream=None):
+                           out_pot=None, potential=True, stream=None, workspace=None):
     import torch
     N, p_pos, p_m, p_e = _sources(pos, mass, eps)
     T = N if targets is None else targets.numel()
@@ -601,9 +669,13 @@ def steps_cyl_forces_table(pos, mass, eps, L, table, order=2, targets=None, out_
     p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * T)
     p_pot = _dev(out_pot, torch.float32, "out_pot", T) if potential else None
     h = table.handle if isinstance(table, CorrectionTable) else table
-    _check(lib().steps_cyl_forces_table(p_pos, p_m, p_e, N, float(L), h, int(order), p_t, T,
-                                        p_acc, p_pot, _stream(stream, pos.device)))
+    _call("steps_cyl_forces_table", (p_pos, p_m, p_e, N, float(L), h, int(order), p_t, T, p_acc, p_pot),
+          _stream(stream, pos.device), workspace)
     return out_acc, (out_pot if potential else None)
+
+
+def steps_cyl_forces_table_ws(pos, mass, eps, L, table, workspace, **kw):
+    return steps_cyl_forces_table(pos, mass, eps, L, table, workspace=workspace, **kw)
 
 
 # ---------------------------------------------------------------- octree

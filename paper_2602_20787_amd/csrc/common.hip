@@ -56,6 +56,13 @@ int require_device() {
     return STEPS_OK;
 }
 
+int check_workspace(const Workspace &ws, size_t need) {
+    if (need > 0 && (!ws.base || ws.size < need))
+        return fail(STEPS_EINVAL, "workspace of %zu bytes is smaller than the %zu bytes this call needs", ws.size,
+                    need);
+    return STEPS_OK;
+}
+
 }  // namespace steps
 
 STEPS_API const char *steps_cyl_last_error(void) { return steps::last_error(); }

@@ -173,7 +173,7 @@ hipError_t launch_nimg(const ExactArgs &a, hipStream_t stream) {
 // Launches the FP32 exact-force kernel; arguments already validated.
 int launch_forces_exact(const double *pos, const double *mass, const double *eps, int64_t N,
                         double L, int n_img, const int64_t *targets, int64_t n_tgt, int mode,
-                        float *out_acc, float *out_pot, hipStream_t stream) {
+                        float *out_acc, float *out_pot, Workspace &ws, hipStream_t stream) {
     ExactArgs a;
     a.x = pos;
     a.y = pos + N;
@@ -195,19 +195,17 @@ int launch_forces_exact(const double *pos, const double *mass, const double *eps
     a.N = (int)N;
     a.n_tgt = (int)n_tgt;
     a.perm = nullptr;
-    // walk the targets in spatial order (scratch is stream-ordered)
-    void *scratch = nullptr;
-    if (n_tgt >= kOrderTargetsMin) {
-        const int rc = order_targets(pos, N, L, targets, n_tgt, stream, &scratch, &a.perm);
-        if (rc) return rc;
-    }
+    // walk the targets in spatial order (keys and order in the workspace)
+    int rc = check_workspace(ws, per_target_bytes(n_tgt));
+    if (rc) return rc;
+    if (n_tgt >= kOrderTargetsMin && (rc = order_targets(pos, N, L, targets, n_tgt, stream, ws, &a.perm)))
+        return rc;
     hipError_t e;
     const bool comp = (mode == STEPS_SUM_COMPENSATED);
     if (out_pot)
         e = comp ? launch_nimg<true, true>(a, stream) : launch_nimg<true, false>(a, stream);
     else
         e = comp ? launch_nimg<false, true>(a, stream) : launch_nimg<false, false>(a, stream);
-    if (scratch) (void)hipFreeAsync(scratch, stream);
     return hip_status(e, "forces_exact launch");
 }
 

@@ -247,7 +247,7 @@ const Packed *packed_of(const steps_cyl_mlp *net);
 
 int launch_forces_learned(const double *pos, const double *mass, const double *eps, int64_t N, double L,
                           const steps_cyl_mlp *net, const int64_t *targets, int64_t n_tgt, int mode,
-                          float *out_acc, float *out_pot, hipStream_t stream) {
+                          float *out_acc, float *out_pot, Workspace &ws, hipStream_t stream) {
     LearnedArgs a;
     a.x = pos;
     a.y = pos + N;
@@ -272,19 +272,17 @@ int launch_forces_learned(const double *pos, const double *mass, const double *e
     a.N = (int)N;
     a.n_tgt = (int)n_tgt;
     a.perm = nullptr;
-    // walk the targets in spatial order (scratch is stream-ordered)
-    void *scratch = nullptr;
-    if (n_tgt >= kOrderTargetsMin) {
-        const int rc = order_targets(pos, N, L, targets, n_tgt, stream, &scratch, &a.perm);
-        if (rc) return rc;
-    }
+    // walk the targets in spatial order (keys and order in the workspace)
+    int rc = check_workspace(ws, per_target_bytes(n_tgt));
+    if (rc) return rc;
+    if (n_tgt >= kOrderTargetsMin && (rc = order_targets(pos, N, L, targets, n_tgt, stream, ws, &a.perm)))
+        return rc;
     const bool comp = (mode == STEPS_SUM_COMPENSATED);
     hipError_t e;
     if (out_pot)
         e = comp ? launch_t<true, true>(a, stream) : launch_t<true, false>(a, stream);
     else
         e = comp ? launch_t<false, true>(a, stream) : launch_t<false, false>(a, stream);
-    if (scratch) (void)hipFreeAsync(scratch, stream);
     return hip_status(e, "forces_learned launch");
 }
 
@@ -294,63 +292,101 @@ int launch_forces_learned(const double *pos, const double *mass, const double *e
 // exact one (R_z is sign(d) times a function of |d| and rho, R_rho a
 // function of |d| and rho), so the reaction is the action with dx, dy and
 // F_z negated (F_z keeps its sign where both particles take the minimum
-// image -L/2).  Groups of 128 particles in spatial order (a workgroup's
-// 4 waves x 32 columns) pair as in the pairwise exact path; the reactions on
-// a source are summed over the 32 lanes of its half-wave, then over the 4
-// waves in LDS, and added to FP64 device sums atomically.  Both sides are
-// summed in FP64 (sources in spatial order would cost FP32 partials their
-// cancellation).
+// image -L/2).
+//
+// Schedule (no atomics, bitwise reproducible).  Particles in spatial order
+// form sub-groups of 128 (a workgroup's 4 waves x 32 columns) and groups of
+// kSubs sub-groups.  The groups meet on the schedule of the pairwise exact
+// path: a first launch pairs every group with itself (one-sided, every
+// ordered pair, the self pair skipped), then G' - 1 launches (G' = G rounded
+// up to even) follow the round-robin tournament in which round r pairs group
+// G'-1 with group r and group (r + k) mod (G'-1) with group (r - k) mod
+// (G'-1).  A meeting of groups A and B takes kSubs^2 workgroups, workgroup
+// (i, j) holding sub-group i of A as targets and streaming sub-group j of B:
+// it adds its actions to slot j of the sums of a_i and the reactions to slot
+// kSubs + i of the sums of b_j.  No group appears twice in a launch, so each
+// slot has one writer per launch and every sum is a plain read-modify-write
+// in an order fixed by N.  A launch holds kSubs^2 G'/2 workgroups of equal
+// size, so one slow meeting (a near pair of groups, with many pairs outside
+// the network's domain) is a small part of it.  The reactions on a source
+// are summed over the 32 lanes of its half-wave, then over the 4 waves in
+// LDS.  Both sides are summed in FP64 (sources in spatial order would cost
+// FP32 partials their cancellation).
 namespace {
 
-constexpr int kOwn = 128;  // particles per group, one per wave column
+constexpr int kOwn = 128;  // particles per sub-group, one per wave column
+constexpr int kSubs = 4;   // sub-groups per group
+constexpr int kSlots = 2 * kSubs;  // sums per particle: actions by source sub-group, reactions by target sub-group
 
 struct PairwiseLearnedArgs {
     LearnedArgs la;   // L, invL, halfL, invLf, invL2f, c, P of the per-target kernel
     const SrcRec *rec;
-    double *acc;      // [4][N] in spatial order
+    double *acc;      // [kSlots][4][N] in spatial order
     double tie;
     float tie32;
-    int N, G, P;
+    int N, G, Gp;     // particles, groups (of kSubs sub-groups), groups rounded up to even
+    int round;        // tournament round (meeting launches)
 };
 
 __global__ void lp_stage_kernel(const double *pos, const double *mass, const double *eps, int N, double L,
-                                const int *perm, SrcRec *rec, double *acc) {
+                                const int *perm, SrcRec *rec) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const int p = perm[k];
     SrcRec r;
     r.x = pos[p];
-    r.y = pos[N + p];
-    r.z = wrap_z(pos[2 * N + p], L);
+    r.y = pos[(int64_t)N + p];
+    r.z = wrap_z(pos[2 * (int64_t)N + p], L);
     r.m = (float)mass[p];
     r.h = (float)eps[p];
     rec[k] = r;
-    for (int c = 0; c < 4; ++c) acc[c * (int64_t)N + k] = 0.0;
 }
 
 __global__ void lp_finish_kernel(const double *acc, const int *perm, int N, float *ax, float *ay, float *az,
                                  float *pot) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < kSlots; ++q)
+        for (int c = 0; c < 4; ++c) v[c] += acc[((int64_t)q * 4 + c) * N + k];
     const int p = perm[k];
-    ax[p] = (float)(-acc[k]);
-    ay[p] = (float)(-acc[N + k]);
-    az[p] = (float)(-acc[2 * (int64_t)N + k]);
-    if (pot) pot[p] = (float)(-acc[3 * (int64_t)N + k]);
+    ax[p] = (float)(-v[0]);
+    ay[p] = (float)(-v[1]);
+    az[p] = (float)(-v[2]);
+    if (pot) pot[p] = (float)(-v[3]);
 }
 
-template <bool POT>
+// Workgroup (i, j) of one meeting (REACT: the groups of tournament round
+// pa.round) or of one group's meeting with itself.
+template <bool POT, bool REACT>
 __global__ __launch_bounds__(kBlock, 2) void forces_learned_pairwise_kernel(PairwiseLearnedArgs pa) {
     __shared__ mlp::Packed P;
     __shared__ SrcRec tile[kOwn];
     __shared__ double jpart[kBlock / 64][kOwn][4];
     const LearnedArgs &a = pa.la;
+    const int meet = blockIdx.x / (kSubs * kSubs);
+    const int si = (blockIdx.x / kSubs) % kSubs, sj = blockIdx.x % kSubs;
+    int ga = meet, gb = meet;
+    if (REACT) {
+        const int M = pa.Gp - 1;
+        if (meet == 0) {
+            ga = M;
+            gb = pa.round;
+        } else {
+            ga = (pa.round + meet) % M;
+            gb = (pa.round - meet + M) % M;
+        }
+        if (ga >= pa.G || gb >= pa.G) return;  // the empty group of an odd count (whole workgroup)
+    }
+    // target sub-group ga*kSubs + si, source sub-group gb*kSubs + sj
+    const int ta = ga * kSubs + si, sb = gb * kSubs + sj;
+    if ((int64_t)ta * kOwn >= pa.N) return;                   // no targets (whole workgroup)
+    if (REACT && (int64_t)sb * kOwn >= pa.N) return;          // no sources: nothing to add
     mlp::load_packed(&P, a.P);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int col = lane & 31, h = lane >> 5;
-    const int g = blockIdx.x / pa.P, qb = blockIdx.x % pa.P;
-    const int64_t t64 = (int64_t)g * kOwn + wave * 32 + col;
+    const int64_t t64 = (int64_t)ta * kOwn + wave * 32 + col;
     const bool active = t64 < pa.N;
     const int t = active ? (int)t64 : pa.N;
     // an empty slot sits far away with no mass: no reaction, never written
@@ -367,104 +403,97 @@ __global__ __launch_bounds__(kBlock, 2) void forces_learned_pairwise_kernel(Pair
     // this half's sums for target `col` (h = 0: even sources, h = 1: odd)
     double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
 
-    const int half = pa.G / 2;
-    const int K = (pa.G & 1) ? half : half - 1 + (g < half ? 1 : 0);
-    const int U = K + 1;
-    const int u0 = (int)((int64_t)qb * U / pa.P), u1 = (int)((int64_t)(qb + 1) * U / pa.P);
-    for (int u = u0; u < u1; ++u) {
-        const int base = ((g + u) % pa.G) * kOwn;
-        const int cnt = min(kOwn, pa.N - base);
-        const bool react = u != 0;
-        __syncthreads();  // the previous tile and its reactions are consumed
-        if (tid < cnt) tile[tid] = pa.rec[base + tid];
-        __syncthreads();
-        for (int s = 0; s < cnt; s += 2) {
-            const bool live = (s + h) < cnt;
-            const int js = live ? (s + h) : s;
-            const SrcRec src = tile[js];
-            const bool self = !react && (base + js == t);
-            PairState q = pair_state<POT>(src, self, live, xi, yi, zi, hi, a);
-            const float g1 = __shfl_xor(q.f1, 32), g2 = __shfl_xor(q.f2, 32);
-            const float fa1 = h ? g1 : q.f1, fa2 = h ? g2 : q.f2;
-            const float fb1 = h ? q.f1 : g1, fb2 = h ? q.f2 : g2;
-            int poff = 0;
-            asm volatile("" : "+v"(poff));
-            const mlp::Packed &Pl = *reinterpret_cast<const mlp::Packed *>(
-                reinterpret_cast<const char *>(&P) + poff);
-            float oa0, oa1, ob0, ob1;
-            mlp::forward32<false>(Pl, fa1, fa2, oa0, oa1, nullptr, nullptr);
-            mlp::forward32<false>(Pl, fb1, fb2, ob0, ob1, nullptr, nullptr);
-            const float o0 = h ? ob0 : oa0, o1 = h ? ob1 : oa1;
-            const float mz = __builtin_fmaf(q.sc, o0, q.bz);
-            float Rz = (q.d > 0.f) ? mz : ((q.d < 0.f) ? -mz : 0.f);
-            float Rr = __builtin_fmaf(q.sc, o1, q.br);
-            if (!q.inside) {
-                Rz = 0.f;
-                Rr = 0.f;
-            }
-            uint64_t outside = __ballot(q.band && active);
-            while (outside) {
-                const int c = __builtin_ctzll(outside);
-                outside &= outside - 1;
-                const float dc = __shfl(q.d * a.invLf, c), rc = __shfl(q.r, c);
-                float tz, tr;
-                band_cooperative(dc, rc, tz, tr);
-                if (lane == c) {
-                    Rz = tz;
-                    Rr = tr;
-                }
-            }
-            const float rinv = q.rho > 0.f ? __builtin_amdgcn_rcpf(q.rho) : 0.f;
-            const double Seff = (double)__builtin_fmaf(-Rr * a.invL2f, rinv, q.S);
-            const double Fzeff = (double)__builtin_fmaf(-Rz, a.invL2f, q.Fz);
-            const double Pn = (double)q.Pn;
-            const double mj = (double)q.m;  // 0 past the tile's end
-            sx = __builtin_fma(mj * Seff, (double)q.dx, sx);
-            sy = __builtin_fma(mj * Seff, (double)q.dy, sy);
-            sz = __builtin_fma(mj, Fzeff, sz);
-            if (POT) sp = __builtin_fma(mj, Pn, sp);
-            if (react) {
-                // the source sees -dx, -dy and -d, except where |d| = L/2 up to
-                // rounding and its own minimum image has the sign of d
-                double fz = Fzeff;
-                if (__builtin_fabsf(q.d) >= pa.tie32) {
-                    const double d64 = min_image(zi - src.z, a.L, a.invL);
-                    if (__builtin_fabs(__builtin_fabs(d64) - a.halfL) <= pa.tie) {
-                        const double dji = min_image(src.z - zi, a.L, a.invL);
-                        if ((dji < 0.0) == (d64 < 0.0)) fz = -Fzeff;
-                    }
-                }
-                const double w = live ? (double)mi : 0.0;
-                double jx = w * Seff * (double)q.dx, jy = w * Seff * (double)q.dy, jz = w * fz;
-                double jp = POT ? w * Pn : 0.0;
-                // sum over the 32 targets of this half
-#pragma unroll
-                for (int off = 16; off >= 1; off >>= 1) {
-                    jx += __shfl_xor(jx, off);
-                    jy += __shfl_xor(jy, off);
-                    jz += __shfl_xor(jz, off);
-                    if (POT) jp += __shfl_xor(jp, off);
-                }
-                if (col == 0 && live) {
-                    jpart[wave][s + h][0] = jx;
-                    jpart[wave][s + h][1] = jy;
-                    jpart[wave][s + h][2] = jz;
-                    jpart[wave][s + h][3] = jp;
-                }
+    const int base = sb * kOwn;
+    const int cnt = max(0, min(kOwn, pa.N - base));  // 0: an empty sub-group of the self meeting
+    if (tid < cnt) tile[tid] = pa.rec[base + tid];
+    __syncthreads();  // the tile and the parameters are in LDS
+    for (int s = 0; s < cnt; s += 2) {
+        const bool live = (s + h) < cnt;
+        const int js = live ? (s + h) : s;
+        const SrcRec src = tile[js];
+        const bool self = !REACT && (base + js == t);
+        PairState q = pair_state<POT>(src, self, live, xi, yi, zi, hi, a);
+        const float g1 = __shfl_xor(q.f1, 32), g2 = __shfl_xor(q.f2, 32);
+        const float fa1 = h ? g1 : q.f1, fa2 = h ? g2 : q.f2;
+        const float fb1 = h ? q.f1 : g1, fb2 = h ? q.f2 : g2;
+        int poff = 0;
+        asm volatile("" : "+v"(poff));
+        const mlp::Packed &Pl = *reinterpret_cast<const mlp::Packed *>(
+            reinterpret_cast<const char *>(&P) + poff);
+        float oa0, oa1, ob0, ob1;
+        mlp::forward32<false>(Pl, fa1, fa2, oa0, oa1, nullptr, nullptr);
+        mlp::forward32<false>(Pl, fb1, fb2, ob0, ob1, nullptr, nullptr);
+        const float o0 = h ? ob0 : oa0, o1 = h ? ob1 : oa1;
+        const float mz = __builtin_fmaf(q.sc, o0, q.bz);
+        float Rz = (q.d > 0.f) ? mz : ((q.d < 0.f) ? -mz : 0.f);
+        float Rr = __builtin_fmaf(q.sc, o1, q.br);
+        if (!q.inside) {
+            Rz = 0.f;
+            Rr = 0.f;
+        }
+        uint64_t outside = __ballot(q.band && active);
+        while (outside) {
+            const int c = __builtin_ctzll(outside);
+            outside &= outside - 1;
+            const float dc = __shfl(q.d * a.invLf, c), rc = __shfl(q.r, c);
+            float tz, tr;
+            band_cooperative(dc, rc, tz, tr);
+            if (lane == c) {
+                Rz = tz;
+                Rr = tr;
             }
         }
-        if (react) {
-            __syncthreads();
-            if (tid < cnt) {
-                const int64_t jj = base + tid;
-                double v[4];
+        const float rinv = q.rho > 0.f ? __builtin_amdgcn_rcpf(q.rho) : 0.f;
+        const double Seff = (double)__builtin_fmaf(-Rr * a.invL2f, rinv, q.S);
+        const double Fzeff = (double)__builtin_fmaf(-Rz, a.invL2f, q.Fz);
+        const double Pn = (double)q.Pn;
+        const double mj = (double)q.m;  // 0 past the tile's end
+        sx = __builtin_fma(mj * Seff, (double)q.dx, sx);
+        sy = __builtin_fma(mj * Seff, (double)q.dy, sy);
+        sz = __builtin_fma(mj, Fzeff, sz);
+        if (POT) sp = __builtin_fma(mj, Pn, sp);
+        if (REACT) {
+            // the source sees -dx, -dy and -d, except where |d| = L/2 up to
+            // rounding and its own minimum image has the sign of d
+            double fz = Fzeff;
+            if (__builtin_fabsf(q.d) >= pa.tie32) {
+                const double d64 = min_image(zi - src.z, a.L, a.invL);
+                if (__builtin_fabs(__builtin_fabs(d64) - a.halfL) <= pa.tie) {
+                    const double dji = min_image(src.z - zi, a.L, a.invL);
+                    if ((dji < 0.0) == (d64 < 0.0)) fz = -Fzeff;
+                }
+            }
+            const double w = live ? (double)mi : 0.0;
+            double jx = w * Seff * (double)q.dx, jy = w * Seff * (double)q.dy, jz = w * fz;
+            double jp = POT ? w * Pn : 0.0;
+            // sum over the 32 targets of this half
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    v[k] = (jpart[0][tid][k] + jpart[1][tid][k]) + (jpart[2][tid][k] + jpart[3][tid][k]);
-                unsafeAtomicAdd(pa.acc + jj, -v[0]);
-                unsafeAtomicAdd(pa.acc + pa.N + jj, -v[1]);
-                unsafeAtomicAdd(pa.acc + 2 * (int64_t)pa.N + jj, -v[2]);
-                if (POT) unsafeAtomicAdd(pa.acc + 3 * (int64_t)pa.N + jj, v[3]);
+            for (int off = 16; off >= 1; off >>= 1) {
+                jx += __shfl_xor(jx, off);
+                jy += __shfl_xor(jy, off);
+                jz += __shfl_xor(jz, off);
+                if (POT) jp += __shfl_xor(jp, off);
+            }
+            if (col == 0 && live) {
+                jpart[wave][s + h][0] = jx;
+                jpart[wave][s + h][1] = jy;
+                jpart[wave][s + h][2] = jz;
+                jpart[wave][s + h][3] = jp;
+            }
+        }
+    }
+    if (REACT) {
+        __syncthreads();
+        if (tid < cnt) {
+            // reaction on source base + tid in the owned sums' orientation:
+            // the 4 waves' parts in order, into the source's slot kSubs + si
+            const int64_t jj = base + tid;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k == 3 && !POT) continue;
+                const double v = (jpart[0][tid][k] + jpart[1][tid][k]) + (jpart[2][tid][k] + jpart[3][tid][k]);
+                double *p = pa.acc + ((int64_t)(kSubs + si) * 4 + k) * pa.N + jj;
+                *p = (k == 3) ? *p + v : *p - v;
             }
         }
     }
@@ -474,30 +503,54 @@ __global__ __launch_bounds__(kBlock, 2) void forces_learned_pairwise_kernel(Pair
     sz += __shfl_xor(sz, 32);
     sp += __shfl_xor(sp, 32);
     if (active && h == 0) {
-        unsafeAtomicAdd(pa.acc + t, sx);
-        unsafeAtomicAdd(pa.acc + pa.N + t, sy);
-        unsafeAtomicAdd(pa.acc + 2 * (int64_t)pa.N + t, sz);
-        if (POT) unsafeAtomicAdd(pa.acc + 3 * (int64_t)pa.N + t, sp);
+        // the targets' actions from sub-group sj: slot sj; the self meeting
+        // initialises it and clears the reaction slot kSubs + sj
+        const double v[4] = {sx, sy, sz, sp};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double *p = pa.acc + ((int64_t)sj * 4 + k) * pa.N + t;
+            if (REACT) {
+                if (k < 3 || POT) *p += v[k];
+            } else {
+                *p = v[k];
+                p[(int64_t)kSubs * 4 * pa.N] = 0.0;
+            }
+        }
     }
+}
+
+template <bool POT>
+hipError_t launch_learned_pairwise(PairwiseLearnedArgs pa, hipStream_t stream) {
+    hipLaunchKernelGGL((forces_learned_pairwise_kernel<POT, false>), dim3(pa.G * kSubs * kSubs), dim3(kBlock), 0,
+                       stream, pa);
+    hipError_t e = hipGetLastError();
+    for (int r = 0; e == hipSuccess && r + 1 < pa.Gp; ++r) {
+        pa.round = r;
+        hipLaunchKernelGGL((forces_learned_pairwise_kernel<POT, true>), dim3(pa.Gp / 2 * kSubs * kSubs), dim3(kBlock),
+                           0, stream, pa);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 }  // namespace
 
+size_t learned_pairwise_bytes(int64_t N) {
+    return ws_total({order_targets_bytes(N), (size_t)N * sizeof(SrcRec), (size_t)N * kSlots * 4 * sizeof(double)});
+}
+
 // Pairwise learned forces of all N particles (see above); arguments already
-// validated.  Scratch (spatial order, records, FP64 sums) is stream-ordered.
+// validated.  Scratch (spatial order, records, FP64 sums) comes from `ws`.
 int launch_forces_learned_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
-                                   const steps_cyl_mlp *net, float *out_acc, float *out_pot, hipStream_t stream) {
-    void *order_scratch = nullptr;
-    const int *perm = nullptr;
-    int rc = order_targets(pos, N, L, nullptr, N, stream, &order_scratch, &perm);
+                                   const steps_cyl_mlp *net, float *out_acc, float *out_pot, Workspace &ws,
+                                   hipStream_t stream) {
+    int rc = check_workspace(ws, learned_pairwise_bytes(N));
     if (rc) return rc;
-    void *buf = nullptr;
-    const size_t bytes = (size_t)N * (sizeof(SrcRec) + 4 * sizeof(double));
-    hipError_t e = hipMallocAsync(&buf, bytes, stream);
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(order_scratch, stream);
-        return fail(STEPS_ENOMEM, "pairwise learned scratch (%zu bytes)", bytes);
-    }
+    const int *perm = nullptr;
+    if ((rc = order_targets(pos, N, L, nullptr, N, stream, ws, &perm))) return rc;
+    SrcRec *rec = (SrcRec *)ws.take((size_t)N * sizeof(SrcRec));
+    double *acc = (double *)ws.take((size_t)N * kSlots * 4 * sizeof(double));
+    if (!rec || !acc) return fail(STEPS_EINVAL, "workspace too small for the pairwise learned path");
     PairwiseLearnedArgs pa;
     LearnedArgs &a = pa.la;
     a.x = a.y = a.z = a.m = a.h = nullptr;
@@ -516,32 +569,23 @@ int launch_forces_learned_pairwise(const double *pos, const double *mass, const 
     a.c.n_img = 1;
     a.N = (int)N;
     a.n_tgt = (int)N;
-    pa.rec = (const SrcRec *)buf;
-    pa.acc = (double *)((char *)buf + (size_t)N * sizeof(SrcRec));
+    pa.rec = rec;
+    pa.acc = acc;
     pa.tie = 1e-12 * L;
     pa.tie32 = (float)(0.5 * L * (1.0 - 1e-6));
     pa.N = (int)N;
-    pa.G = (int)((N + kOwn - 1) / kOwn);
-    const int units = pa.G / 2 + 1;
-    pa.P = std::max(1, std::min(units, (4096 + pa.G - 1) / pa.G));
+    pa.G = (int)((N + kOwn * kSubs - 1) / (kOwn * kSubs));
+    pa.Gp = pa.G + (pa.G & 1);
+    pa.round = 0;
     const int nb = (int)((N + 255) / 256);
-    hipLaunchKernelGGL(lp_stage_kernel, dim3(nb), dim3(256), 0, stream, pos, mass, eps, (int)N, L, perm,
-                       (SrcRec *)buf, pa.acc);
-    e = hipGetLastError();
-    if (e == hipSuccess) {
-        if (out_pot)
-            hipLaunchKernelGGL(forces_learned_pairwise_kernel<true>, dim3(pa.G * pa.P), dim3(kBlock), 0, stream, pa);
-        else
-            hipLaunchKernelGGL(forces_learned_pairwise_kernel<false>, dim3(pa.G * pa.P), dim3(kBlock), 0, stream, pa);
-        e = hipGetLastError();
-    }
+    hipLaunchKernelGGL(lp_stage_kernel, dim3(nb), dim3(256), 0, stream, pos, mass, eps, (int)N, L, perm, rec);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = out_pot ? launch_learned_pairwise<true>(pa, stream) : launch_learned_pairwise<false>(pa, stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(lp_finish_kernel, dim3(nb), dim3(256), 0, stream, pa.acc, perm, (int)N, out_acc,
                            out_acc + N, out_acc + 2 * N, out_pot);
         e = hipGetLastError();
     }
-    (void)hipFreeAsync(buf, stream);
-    (void)hipFreeAsync(order_scratch, stream);
     return hip_status(e, "forces_learned_pairwise launch");
 }
 

@@ -177,8 +177,10 @@ struct WaveBox {
 // box b needs the softening or the half-period screen: the boxes are apart by
 // more than the sum of their largest softenings (with that sum below L/2, so
 // that no image n != 0 is softened either) and no axial separation comes
-// near L/2.  Evaluated alike by every lane.
-__device__ __forceinline__ bool far_boxes(const PairwiseArgs &a, const WaveBox &w, const double *b) {
+// near L/2.  Then every axial separation t = z_i - z_j of the two boxes has
+// the same minimum image t - kL, returned as kL.  Evaluated alike by every
+// lane.
+__device__ __forceinline__ bool far_boxes(const PairwiseArgs &a, const WaveBox &w, const double *b, double &kL) {
     const double hs = w.h + b[6];
     if (hs > a.far_h) return false;
     const double gx = fmax(0.0, fmax(w.x0 - b[1], b[0] - w.x1));
@@ -195,28 +197,143 @@ __device__ __forceinline__ bool far_boxes(const PairwiseArgs &a, const WaveBox &
     // no separation within 1e-5 L of a half period (the screen is 5e-7 L)
     const double m = 1e-5 * a.L;
     if (ceil((tl - m) * a.invL - 0.5) <= floor((th + m) * a.invL - 0.5)) return false;
+    kL = a.L * floor(tl * a.invL + 0.5);
     return gx * gx + gy * gy + gz * gz > hs * hs * (1.0 + 1e-4) + 1e-300;
 }
 
-// LDS of a workgroup: the tile's sources (SoA) and the waves' reaction slots.
+// LDS of a workgroup: the tile's sources (SoA) and the waves' FP64 reaction
+// slots.
 struct Stage {
     double x[kTile], y[kTile], z[kTile];
     float m[kTile], h[kTile];
-    double r[kWaves][4][kTile];
+    double r[kWaves][4][kTile];  // reactions, FP64
 };
 
-// One wave's rotation over sub-tile s: 64 steps, lane l taking source
-// (l + step) mod 64.  REACT: the sources belong to another group; their
-// reactions (in the owned sums' orientation, dx = x_i - x_j) are summed in the
-// wave's LDS slots.  Otherwise (the group against itself) the self pair is
-// skipped.  FAST: the sub-tile is far from the wave's particles (far_boxes),
-// so neither the softening nor the half-period screen can trigger.  Pair
-// terms are FP32, sums FP64 (the records are in spatial order, so a
-// particle's near neighbours arrive together and an FP32 partial would lose
-// their cancellation).
-template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT, bool FAST, int kR>
-__device__ __forceinline__ void sub_pass(const PairwiseArgs &a, const Owned<kR> &o, Stage &st, int s, int base,
-                                         float hmax, double (*acc)[4]) {
+// Reaction on the source from an evaluated pair, in the owned sums'
+// orientation (dx = x_i - x_j): the source sees -dx, -dy and -d, except
+// where |d| = L/2 up to rounding and its own minimum image has the sign of d.
+__device__ __forceinline__ double tie_fz(const PairwiseArgs &a, double zi, double zj, double Fz64) {
+    const double d64 = min_image(zi - zj, a.L, a.invL);
+    if (__builtin_fabs(__builtin_fabs(d64) - a.halfL) <= a.tie) {
+        const double dji = min_image(zj - zi, a.L, a.invL);
+        if ((dji < 0.0) == (d64 < 0.0)) return -Fz64;
+    }
+    return Fz64;
+}
+
+// The table's far images of one pair (Sect. 2.2, eq. S1R2EwaldCorrectionTable)
+// added to (S, Fz): R_z is odd in d and R_rho even, so the corrected pair
+// keeps the symmetry of the exact one.  `self`: the pair of a particle with
+// itself (no correction).
+template <int TORDER, bool COMPLETE>
+__device__ __forceinline__ void table_far(const PairwiseArgs &a, float dx, float dy, float d, bool self, float &S,
+                                          float &Fz) {
+    const float rho = __builtin_sqrtf(__builtin_fmaf(dx, dx, dy * dy));
+    const float rr = rho * a.invLf;
+    const float delta = __builtin_fabsf(d) * a.invLf;
+    const bool inside = (rr <= a.tv.r_max) && !self;
+    float tz, tr;
+    lookup<(TORDER > 0 ? TORDER : 1)>(a.tv, delta, inside ? rr : 0.f, tz, tr);
+    float Rz = (d > 0.f) ? tz : ((d < 0.f) ? -tz : 0.f);
+    float Rr = tr;
+    if (!inside) {
+        Rz = 0.f;
+        Rr = 0.f;
+        if (!self) {
+            const float ds = d * a.invLf;
+            if (COMPLETE) {
+                // line-mass limit of the complete sum minus the images |n| <= 1
+                const float r2 = rr * rr;
+                float nz = 0.f, nr = 0.f;
+#pragma unroll
+                for (int n = -1; n <= 1; ++n) {
+                    const float u = ds - (float)n;
+                    const float iq = __builtin_amdgcn_rsqf(__builtin_fmaf(u, u, r2));
+                    const float iq3 = iq * iq * iq;
+                    nz = __builtin_fmaf(-u, iq3, nz);
+                    nr = __builtin_fmaf(-rr, iq3, nr);
+                }
+                Rz = -nz;
+                Rr = -2.f * __builtin_amdgcn_rcpf(rr) - nr;
+            } else {
+                band_serial(ds, rr, a.tv.n_far, Rz, Rr);
+            }
+        }
+    }
+    const float rinv = rho > 0.f ? __builtin_amdgcn_rcpf(rho) : 0.f;
+    S = __builtin_fmaf(-Rr * a.invL2f, rinv, S);
+    Fz = __builtin_fmaf(-Rz, a.invL2f, Fz);
+}
+
+// One wave's rotation over sub-tile s when far_boxes holds (image shift kL):
+// 64 steps, lane l taking source (l + step) mod 64.  The separation is the
+// FP64 difference of the positions, with the minimum image's shift kL taken
+// off the owned z once per sub-tile, rounded to FP32 (as exact as in
+// near_pass, with no per-pair floor).  No softening, no half-period screen.
+// FP32 pair terms, FP64 sums and reactions as in near_pass.
+template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT, int kR>
+__device__ __forceinline__ void far_pass(const PairwiseArgs &a, const Owned<kR> &o, Stage &st, int s, double kL,
+                                         double (*acc)[4]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double zs[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) zs[r] = o.z[r] - kL;
+    for (int step = 0; step < kSub; ++step) {
+        const int k = (s << 6) | ((lane + step) & 63);
+        const double sxj = st.x[k], syj = st.y[k], szj = st.z[k];
+        const double ms = (double)st.m[k];
+        double jx = 0.0, jy = 0.0, jz = 0.0, jp = 0.0;
+        if (REACT && step > 0) {
+            // the slot as the previous lane left it
+            jx = st.r[wave][0][k];
+            jy = st.r[wave][1][k];
+            jz = st.r[wave][2][k];
+            if (POT) jp = st.r[wave][3][k];
+        }
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const double dx64 = o.x[r] - sxj, dy64 = o.y[r] - syj;
+            const float dx = (float)dx64, dy = (float)dy64, d = (float)(zs[r] - szj);
+            float S, Fz, P = 0.f;
+            pair_fast<NIMG, POT>(dx, dy, d, a.c, S, Fz, P);
+            if (TORDER > 0) table_far<TORDER, COMPLETE>(a, dx, dy, d, false, S, Fz);
+            const double S64 = (double)S, Fz64 = (double)Fz;
+            const double mS = ms * S64;
+            acc[r][0] = __builtin_fma(mS, dx64, acc[r][0]);
+            acc[r][1] = __builtin_fma(mS, dy64, acc[r][1]);
+            acc[r][2] = __builtin_fma(ms, Fz64, acc[r][2]);
+            if (POT) acc[r][3] = __builtin_fma(ms, (double)P, acc[r][3]);
+            if (REACT) {
+                const double miS = o.m[r] * S64;
+                jx = __builtin_fma(miS, dx64, jx);
+                jy = __builtin_fma(miS, dy64, jy);
+                jz = __builtin_fma(o.m[r], Fz64, jz);
+                if (POT) jp = __builtin_fma(o.m[r], (double)P, jp);
+            }
+        }
+        if (REACT) {
+            st.r[wave][0][k] = jx;
+            st.r[wave][1][k] = jy;
+            st.r[wave][2][k] = jz;
+            if (POT) st.r[wave][3][k] = jp;
+        }
+    }
+}
+
+// One wave's rotation over sub-tile s in general position: FP64 separation
+// and minimum image, then FP32 pair terms and FP64 sums (the records are in
+// spatial order, so a particle's near neighbours arrive together and an FP32
+// partial would lose their cancellation).  The n = 0 image of a pair inside
+// its softening length takes the spline in FP32 (selected per pair; the
+// separation is the FP64 one cast); with a softening sum above L/2 the
+// images n != 0 may be softened too and the pair is evaluated in FP64 with
+// the spline on every image (rare: one pair per lane and pass).  REACT: the
+// sources belong to another group and their reactions are summed in the
+// wave's FP64 LDS slots; otherwise (the group against itself) the self pair
+// is skipped.
+template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT, int kR>
+__device__ __forceinline__ void near_pass(const PairwiseArgs &a, const Owned<kR> &o, Stage &st, int s, int base,
+                                          float hmax, double (*acc)[4]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float thr2[kR];
     bool wide[kR];
@@ -237,7 +354,7 @@ __device__ __forceinline__ void sub_pass(const PairwiseArgs &a, const Owned<kR> 
         double dx64[kR], dy64[kR];
         float S[kR], Fz[kR], P[kR], dr[kR];
         bool tie[kR];
-        unsigned soft = 0;  // bit r: the pair (r, src) takes the FP64 spline
+        unsigned soft64 = 0;  // bit r: the pair (r, src) takes the FP64 spline on every image
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
             dx64[r] = o.x[r] - src.x;
@@ -245,95 +362,68 @@ __device__ __forceinline__ void sub_pass(const PairwiseArgs &a, const Owned<kR> 
             const double d64 = min_image(o.z[r] - src.z, a.L, a.invL);
             const float dx = (float)dx64[r], dy = (float)dy64[r], d = (float)d64;
             dr[r] = d;
-            P[r] = 0.f;
-            pair_fast<NIMG, POT>(dx, dy, d, a.c, S[r], Fz[r], P[r]);
-            tie[r] = false;
-            if (!FAST) {
-                const float r2_0 = __builtin_fmaf(d, d, __builtin_fmaf(dx, dx, dy * dy));
-                const float hij = o.h[r] + src.h;
-                if ((wide[r] || r2_0 < thr2[r]) && (r2_0 < hij * hij || hij > (float)a.halfL)) soft |= 1u << r;
-                tie[r] = REACT && __builtin_fabsf(d) >= a.tie32;
+            const float rho2 = __builtin_fmaf(dx, dx, dy * dy);
+            const float r2_0 = __builtin_fmaf(d, d, rho2);
+            float T, U, Q;
+            pair_images<NIMG, POT>(rho2, d, r2_0, a.c, T, U, Q);
+            const float hij = o.h[r] + src.h;
+            const bool self = !REACT && base + k == o.t[r];
+            const bool near = (wide[r] || r2_0 < thr2[r]) && (r2_0 < hij * hij || hij > (float)a.halfL);
+            if (near && hij > (float)a.halfL && !self) soft64 |= 1u << r;
+            float s0, p0;
+            if (__ballot(near && !self) != 0) {
+                float sf, pf;
+                spline_n0(r2_0, hij, sf, pf);
+                const float ri0 = __builtin_amdgcn_rsqf(r2_0);
+                s0 = near ? sf : ri0 * ri0 * ri0;
+                p0 = near ? pf : ri0;
+            } else {
+                const float ri0 = __builtin_amdgcn_rsqf(r2_0);
+                s0 = ri0 * ri0 * ri0;
+                p0 = ri0;
             }
+            S[r] = s0 + T;
+            Fz[r] = __builtin_fmaf(d, S[r], -a.c.Lf * U);
+            P[r] = p0 + Q;
+            if (self) {
+                // j == i: no term at all, images included
+                S[r] = 0.f;
+                Fz[r] = 0.f;
+                P[r] = 0.f;
+            }
+            tie[r] = REACT && __builtin_fabsf(d) >= a.tie32;
         }
-        if (!FAST) {
-            while (soft) {
-                // rare and divergent: one pair per lane and pass, operands
-                // picked by selects so that the spline code exists once
-                const int rr = __builtin_ctz(soft);
-                soft &= soft - 1;
-                double xr = o.x[0], yr = o.y[0], zr = o.z[0];
-                float hr = o.h[0];
-                int tr = o.t[0];
+        while (soft64) {
+            // rare and divergent: one pair per lane and pass, operands picked
+            // by selects so that the spline code exists once
+            const int rr = __builtin_ctz(soft64);
+            soft64 &= soft64 - 1;
+            double xr = o.x[0], yr = o.y[0], zr = o.z[0];
+            float hr = o.h[0];
 #pragma unroll
-                for (int q = 1; q < kR; ++q)
-                    if (rr == q) {
-                        xr = o.x[q];
-                        yr = o.y[q];
-                        zr = o.z[q];
-                        hr = o.h[q];
-                        tr = o.t[q];
-                    }
-                float gS = 0.f, gF = 0.f, gP = 0.f;
-                if (REACT || base + k != tr) {
-                    double gs, gf, gp;
-                    pair_spline_f64(xr - src.x, yr - src.y, min_image(zr - src.z, a.L, a.invL),
-                                    (double)hr + (double)src.h, a.L, (NIMG >= 0) ? NIMG : a.c.n_img, gs, gf, gp);
-                    gS = (float)gs;
-                    gF = (float)gf;
-                    gP = (float)gp;
+            for (int q = 1; q < kR; ++q)
+                if (rr == q) {
+                    xr = o.x[q];
+                    yr = o.y[q];
+                    zr = o.z[q];
+                    hr = o.h[q];
                 }
+            double gs, gf, gp;
+            pair_spline_f64(xr - src.x, yr - src.y, min_image(zr - src.z, a.L, a.invL),
+                            (double)hr + (double)src.h, a.L, (NIMG >= 0) ? NIMG : a.c.n_img, gs, gf, gp);
 #pragma unroll
-                for (int q = 0; q < kR; ++q)
-                    if (rr == q) {
-                        S[q] = gS;
-                        Fz[q] = gF;
-                        P[q] = gP;
-                    }
-            }
+            for (int q = 0; q < kR; ++q)
+                if (rr == q) {
+                    S[q] = (float)gs;
+                    Fz[q] = (float)gf;
+                    P[q] = (float)gp;
+                }
         }
         if (TORDER > 0) {
-            // far images from the table (Sect. 2.2, eq. S1R2EwaldCorrectionTable):
-            // R_z is odd in d and R_rho even, so the corrected pair keeps the
-            // symmetry of the exact one
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
-                const float dx = (float)dx64[r], dy = (float)dy64[r];
-                const float rho = __builtin_sqrtf(__builtin_fmaf(dx, dx, dy * dy));
-                const float rr = rho * a.invLf;
-                const float delta = __builtin_fabsf(dr[r]) * a.invLf;
                 const bool self = !REACT && base + k == o.t[r];
-                const bool inside = (rr <= a.tv.r_max) && !self;
-                float tz, tr;
-                lookup<(TORDER > 0 ? TORDER : 1)>(a.tv, delta, inside ? rr : 0.f, tz, tr);
-                float Rz = (dr[r] > 0.f) ? tz : ((dr[r] < 0.f) ? -tz : 0.f);
-                float Rr = tr;
-                if (!inside) {
-                    Rz = 0.f;
-                    Rr = 0.f;
-                    if (!self) {
-                        const float ds = dr[r] * a.invLf;
-                        if (COMPLETE) {
-                            // line-mass limit of the complete sum minus the images |n| <= 1
-                            const float r2 = rr * rr;
-                            float nz = 0.f, nr = 0.f;
-#pragma unroll
-                            for (int n = -1; n <= 1; ++n) {
-                                const float u = ds - (float)n;
-                                const float iq = __builtin_amdgcn_rsqf(__builtin_fmaf(u, u, r2));
-                                const float iq3 = iq * iq * iq;
-                                nz = __builtin_fmaf(-u, iq3, nz);
-                                nr = __builtin_fmaf(-rr, iq3, nr);
-                            }
-                            Rz = -nz;
-                            Rr = -2.f * __builtin_amdgcn_rcpf(rr) - nr;
-                        } else {
-                            band_serial(ds, rr, a.tv.n_far, Rz, Rr);
-                        }
-                    }
-                }
-                const float rinv = rho > 0.f ? __builtin_amdgcn_rcpf(rho) : 0.f;
-                S[r] = __builtin_fmaf(-Rr * a.invL2f, rinv, S[r]);
-                Fz[r] = __builtin_fmaf(-Rz, a.invL2f, Fz[r]);
+                table_far<TORDER, COMPLETE>(a, (float)dx64[r], (float)dy64[r], dr[r], self, S[r], Fz[r]);
             }
         }
         const double ms = (double)src.m;
@@ -354,16 +444,7 @@ __device__ __forceinline__ void sub_pass(const PairwiseArgs &a, const Owned<kR> 
             acc[r][2] = __builtin_fma(ms, Fz64, acc[r][2]);
             if (POT) acc[r][3] = __builtin_fma(ms, (double)P[r], acc[r][3]);
             if (REACT) {
-                // the source sees -dx, -dy and -d, except where |d| = L/2 up to
-                // rounding and its own minimum image has the sign of d
-                double fz = Fz64;
-                if (!FAST && tie[r]) {
-                    const double d64 = min_image(o.z[r] - src.z, a.L, a.invL);
-                    if (__builtin_fabs(__builtin_fabs(d64) - a.halfL) <= a.tie) {
-                        const double dji = min_image(src.z - o.z[r], a.L, a.invL);
-                        if ((dji < 0.0) == (d64 < 0.0)) fz = -Fz64;
-                    }
-                }
+                const double fz = tie[r] ? tie_fz(a, o.z[r], src.z, Fz64) : Fz64;
                 const double miS = o.m[r] * S64;
                 jx = __builtin_fma(miS, dx64[r], jx);
                 jy = __builtin_fma(miS, dy64[r], jy);
@@ -383,7 +464,7 @@ __device__ __forceinline__ void sub_pass(const PairwiseArgs &a, const Owned<kR> 
 // One meeting (REACT: group a against chunk q of group b in tournament round
 // a.round) or one self meeting (group a against chunk q of itself).
 template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT>
-__global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseArgs a) {
+__global__ __launch_bounds__(kThreads, TORDER > 0 ? 3 : 2) void forces_pairwise_kernel(PairwiseArgs a) {
     constexpr int kR = particles_per_thread(TORDER);
     constexpr int kGroup = kThreads * kR;  // particles per group
     __shared__ Stage st;
@@ -470,13 +551,13 @@ __global__ __launch_bounds__(kThreads, 2) void forces_pairwise_kernel(PairwiseAr
         }
         __syncthreads();
         for (int s = 0; s < nsub; ++s) {
-            const double *b = a.box + (int64_t)((base >> 6) + s) * kBox;  // base is a multiple of 64
-            const bool fast = far_boxes(a, wb, b);
-            const float hmax = (float)b[6];
-            if (__builtin_amdgcn_readfirstlane((int)fast))
-                sub_pass<NIMG, POT, TORDER, COMPLETE, REACT, true>(a, o, st, s, base, hmax, acc);
+            const double *b = a.box + (int64_t)((base >> 6) + s) * kBox;
+            double kL = 0.0;
+            const bool far = far_boxes(a, wb, b, kL);
+            if (__builtin_amdgcn_readfirstlane((int)far))
+                far_pass<NIMG, POT, TORDER, COMPLETE, REACT>(a, o, st, s, kL, acc);
             else
-                sub_pass<NIMG, POT, TORDER, COMPLETE, REACT, false>(a, o, st, s, base, hmax, acc);
+                near_pass<NIMG, POT, TORDER, COMPLETE, REACT>(a, o, st, s, base, (float)b[6], acc);
         }
         __syncthreads();
         if (REACT && tid < cnt) {
@@ -568,37 +649,63 @@ auto dispatch(int n_img, bool pot, int order, bool complete, F &&f) {
 }
 
 // Workgroups per meeting: the smallest P (chunks of kGroup/P sources, at
-// least 64) whose launches fill the resident workgroup slots to within 10%
-// of the best choice.  `resident` is the number of workgroups the device
-// holds at once for the meeting kernel.
+// least one 64-source sub-tile) whose launches hold at least 16 times the
+// workgroups the device keeps resident, else the largest.  A launch ends
+// with its slowest workgroup (a near meeting, with many pairs on the
+// general path), so short workgroups in many waves keep that tail small;
+// each step of P adds one slot of FP64 sums per particle.  `resident` is the
+// number of workgroups the device holds at once for the meeting kernel.
 int choose_P(int Gp, int kGroup, int resident) {
     const int64_t meetings = Gp / 2;
-    double eff[8] = {0};
-    int cand[8], nc = 0;
-    double best = 0.0;
-    for (int P = 1; P <= kGroup / kSub && nc < 8; P *= 2) cand[nc++] = P;
-    for (int i = 0; i < nc; ++i) {
-        const int64_t W = meetings * cand[i];
-        const int64_t waves = (W + resident - 1) / resident;
-        eff[i] = (double)W / (double)(waves * resident);
-        best = std::max(best, eff[i]);
-    }
-    for (int i = 0; i < nc; ++i)
-        if (eff[i] >= 0.9 * best) return cand[i];
-    return 1;
+    int P = 1;
+    while (P < kGroup / kSub && meetings * P < (int64_t)16 * resident) P *= 2;
+    return P;
+}
+
+// Workgroups per meeting (P) and particles per group of a pairwise call on
+// the current device.
+int pairwise_plan(int64_t N, const steps_cyl_table *table, int order, int n_img, bool pot, int *P, int *group) {
+    const int kR = particles_per_thread(table ? 1 : 0);
+    *group = kThreads * kR;
+    const int G = (int)((N + *group - 1) / *group);
+    const int Gp = G + (G & 1);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_status(e, "device attributes");
+    const int ord = table ? order : 0;
+    const bool complete = table && table->complete != 0;
+    const int per_cu = dispatch(table ? 1 : n_img, pot, ord, complete, [](auto l) { return l.blocks_per_cu(); });
+    *P = choose_P(Gp, *group, per_cu * std::max(1, cus));
+    return STEPS_OK;
 }
 
 }  // namespace
 
+size_t pairwise_bytes_P(int64_t N, int P) {
+    const int64_t nbox = (N + 63) / 64;
+    return ws_total({order_targets_bytes(N), (size_t)N * sizeof(SrcRec), (size_t)nbox * kBox * sizeof(double),
+                     (size_t)P * 4 * N * sizeof(double)});
+}
+
+size_t pairwise_bytes(int64_t N, int n_img, const steps_cyl_table *table, int order, bool pot) {
+    int P = 1, group = 0;
+    if (pairwise_plan(N, table, order, n_img, pot, &P, &group) != STEPS_OK) return 0;
+    return pairwise_bytes_P(N, P);
+}
+
 // Launches the pairwise path for all N particles: exact images |n| <= n_img,
 // or (table non-null) images |n| <= 1 plus the table's far images with CIC
 // (order 1) or TSC (order 2) interpolation.  Arguments already validated.
-// Scratch (spatial order, records, boxes, FP64 sums) is stream-ordered.
+// Scratch (spatial order, records, boxes, FP64 sums) comes from `ws`.
 int launch_forces_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
                            int n_img, const steps_cyl_table *table, int order, float *out_acc, float *out_pot,
-                           hipStream_t stream) {
-    const int kR = particles_per_thread(table ? 1 : 0);
-    const int group = kThreads * kR;
+                           Workspace &ws, hipStream_t stream, int p_cap) {
+    int P = 1, group = 0;
+    int rc = pairwise_plan(N, table, order, n_img, out_pot != nullptr, &P, &group);
+    if (rc) return rc;
+    if (p_cap > 0) P = std::min(P, p_cap);
+    if ((rc = check_workspace(ws, pairwise_bytes_P(N, P)))) return rc;
     PairwiseArgs a;
     a.L = L;
     a.invL = 1.0 / L;
@@ -617,38 +724,25 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
     a.G = (int)((N + group - 1) / group);
     a.Gp = a.G + (a.G & 1);
     a.round = 0;
+    a.P = P;
+    a.chunk = group / a.P;
     const int ord = table ? order : 0;
     const bool complete = table && table->complete != 0;
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_status(e, "device attributes");
-    const int per_cu = dispatch(a.c.n_img, out_pot != nullptr, ord, complete, [](auto l) { return l.blocks_per_cu(); });
-    a.P = choose_P(a.Gp, group, per_cu * std::max(1, cus));
-    a.chunk = group / a.P;
 
-    void *order_scratch = nullptr;
     const int *perm = nullptr;
-    int rc = order_targets(pos, N, L, nullptr, N, stream, &order_scratch, &perm);
-    if (rc) return rc;
-    void *buf = nullptr;
+    if ((rc = order_targets(pos, N, L, nullptr, N, stream, ws, &perm))) return rc;
     const int64_t nbox = (N + 63) / 64;
-    const size_t bytes = (size_t)N * sizeof(SrcRec) + (size_t)nbox * kBox * sizeof(double) +
-                         (size_t)a.P * 4 * N * sizeof(double);
-    e = hipMallocAsync(&buf, bytes, stream);
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(order_scratch, stream);
-        return fail(STEPS_ENOMEM, "pairwise scratch (%zu bytes)", bytes);
-    }
-    a.rec = (const SrcRec *)buf;
-    a.box = (const double *)((char *)buf + (size_t)N * sizeof(SrcRec));
-    a.sum = (double *)((char *)buf + (size_t)N * sizeof(SrcRec) + (size_t)nbox * kBox * sizeof(double));
+    SrcRec *rec = (SrcRec *)ws.take((size_t)N * sizeof(SrcRec));
+    double *box = (double *)ws.take((size_t)nbox * kBox * sizeof(double));
+    double *sum = (double *)ws.take((size_t)a.P * 4 * N * sizeof(double));
+    if (!rec || !box || !sum) return fail(STEPS_EINVAL, "workspace too small for the pairwise path");
+    a.rec = rec;
+    a.box = box;
+    a.sum = sum;
     const int nb = (int)((N + 255) / 256);
-    hipLaunchKernelGGL(stage_kernel, dim3(nb), dim3(256), 0, stream, pos, mass, eps, (int)N, L, perm,
-                       (SrcRec *)buf);
-    hipLaunchKernelGGL(box_kernel, dim3((unsigned)((nbox + 3) / 4)), dim3(256), 0, stream, a.rec, (int)N,
-                       (double *)a.box);
-    e = hipGetLastError();
+    hipLaunchKernelGGL(stage_kernel, dim3(nb), dim3(256), 0, stream, pos, mass, eps, (int)N, L, perm, rec);
+    hipLaunchKernelGGL(box_kernel, dim3((unsigned)((nbox + 3) / 4)), dim3(256), 0, stream, a.rec, (int)N, box);
+    hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         e = dispatch(a.c.n_img, out_pot != nullptr, ord, complete, [&](auto l) { return l.run(a, stream); });
     if (e == hipSuccess) {
@@ -656,8 +750,6 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
                            out_acc + N, out_acc + 2 * N, out_pot);
         e = hipGetLastError();
     }
-    (void)hipFreeAsync(buf, stream);
-    (void)hipFreeAsync(order_scratch, stream);
     return hip_status(e, "forces_pairwise launch");
 }
 

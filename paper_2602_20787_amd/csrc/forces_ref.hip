@@ -105,9 +105,29 @@ __global__ void reduce_chunks_kernel(const double *part, int chunks, int n_tgt, 
 
 }  // namespace
 
+// Source chunks of the FP64 reference for n_tgt targets: enough (target
+// block, chunk) pairs to fill the GPU, chunks of at least 256 sources.
+void f64_chunks(int64_t N, int64_t n_tgt, int *chunks, int *chunk) {
+    const int tblocks = (int)((n_tgt + kBlock - 1) / kBlock);
+    int c = (4096 + tblocks - 1) / tblocks;
+    const int max_chunks = (int)((N + kBlock - 1) / kBlock);
+    if (c > max_chunks) c = max_chunks;
+    if (c < 1) c = 1;
+    *chunk = (int)(((N + c - 1) / c + kBlock - 1) / kBlock * kBlock);
+    *chunks = (int)((N + *chunk - 1) / *chunk);
+}
+
+size_t f64_bytes(int64_t N, int64_t n_tgt) {
+    int chunks = 1, chunk = 1;
+    f64_chunks(N, n_tgt, &chunks, &chunk);
+    return ws_total({sizeof(double) * 4 * (size_t)chunks * n_tgt});
+}
+
 int launch_forces_f64(const double *pos, const double *mass, const double *eps, int64_t N, double L,
                       int n_img, const int64_t *targets, int64_t n_tgt, double *out_acc, double *out_pot,
-                      hipStream_t stream) {
+                      Workspace &ws, hipStream_t stream) {
+    int rc = check_workspace(ws, f64_bytes(N, n_tgt));
+    if (rc) return rc;
     RefArgs a;
     a.x = pos;
     a.y = pos + N;
@@ -121,14 +141,10 @@ int launch_forces_f64(const double *pos, const double *mass, const double *eps, 
     a.n_tgt = (int)n_tgt;
     a.n_img = n_img;
     const int tblocks = (int)((n_tgt + kBlock - 1) / kBlock);
-    // enough (target block, chunk) pairs to fill the GPU, chunks of >= 256 sources
-    int chunks = (4096 + tblocks - 1) / tblocks;
-    const int max_chunks = (int)((N + kBlock - 1) / kBlock);
-    if (chunks > max_chunks) chunks = max_chunks;
-    if (chunks < 1) chunks = 1;
-    a.chunk = (int)(((N + chunks - 1) / chunks + kBlock - 1) / kBlock * kBlock);
-    chunks = (int)((N + a.chunk - 1) / a.chunk);
-    STEPS_CHECK_HIP(hipMallocAsync((void **)&a.part, sizeof(double) * 4 * (size_t)chunks * n_tgt, stream));
+    int chunks = 1;
+    f64_chunks(N, n_tgt, &chunks, &a.chunk);
+    a.part = (double *)ws.take(sizeof(double) * 4 * (size_t)chunks * n_tgt);
+    if (!a.part) return fail(STEPS_EINVAL, "workspace too small for the FP64 reference");
     hipLaunchKernelGGL(forces_f64_kernel, dim3(tblocks, chunks), dim3(kBlock), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
@@ -136,9 +152,7 @@ int launch_forces_f64(const double *pos, const double *mass, const double *eps, 
                            (int)n_tgt, out_acc, out_pot);
         e = hipGetLastError();
     }
-    hipError_t f = hipFreeAsync(a.part, stream);
-    if (e != hipSuccess) return hip_status(e, "forces_f64 launch");
-    return hip_status(f, "forces_f64 scratch release");
+    return hip_status(e, "forces_f64 launch");
 }
 
 }  // namespace steps

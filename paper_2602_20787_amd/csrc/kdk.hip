@@ -410,7 +410,10 @@ STEPS_API int steps_cyl_kdk_step(double *pos, double *mom, const double *mass, c
     hipLaunchKernelGGL(drift_kernel, grid, block, 0, stream, pos, mom, N, f[1], L);
     STEPS_CHECK_HIP(hipGetLastError());
     if (params->net)
-        rc = launch_forces_learned_pairwise(pos, mass, eps, N, L, params->net, acc_inout, nullptr, stream);
+        rc = with_stream_workspace(learned_pairwise_bytes(N), stream, [&](Workspace &ws) {
+            return launch_forces_learned_pairwise(pos, mass, eps, N, L, params->net, acc_inout, nullptr, ws,
+                                                  stream);
+        });
     else if (params->tree)
         rc = steps_cyl_tree_forces(params->tree, pos, mass, eps, N, L, params->R_cyl, params->table,
                                    params->table_order, params->theta, params->tree_shift, params->tree_angle,
@@ -419,7 +422,10 @@ STEPS_API int steps_cyl_kdk_step(double *pos, double *mom, const double *mass, c
         rc = steps_cyl_forces_table(pos, mass, eps, N, L, params->table, params->table_order, nullptr, N,
                                     acc_inout, nullptr, stream);
     else
-        rc = launch_forces_pairwise(pos, mass, eps, N, L, params->n_img, nullptr, 0, acc_inout, nullptr, stream);
+        rc = with_stream_workspace(pairwise_bytes(N, params->n_img, nullptr, 0, false), stream, [&](Workspace &ws) {
+            return launch_forces_pairwise(pos, mass, eps, N, L, params->n_img, nullptr, 0, acc_inout, nullptr, ws,
+                                          stream);
+        });
     if (rc) return rc;
     hipLaunchKernelGGL(kick_kernel, grid, block, 0, stream, pos, mom, acc_inout, N, f[2], c, params->compensate);
     return hip_status(hipGetLastError(), "kick kernel");

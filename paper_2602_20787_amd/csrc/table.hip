@@ -388,9 +388,11 @@ STEPS_API int steps_cyl_table_info(const steps_cyl_table *t, int *n_delta, int *
     return STEPS_OK;
 }
 
-STEPS_API int steps_cyl_forces_table(const double *pos, const double *mass, const double *eps, int64_t N,
-                                     double L, const steps_cyl_table *t, int order, const int64_t *targets,
-                                     int64_t n_targets, float *out_acc, float *out_pot, hipStream_t stream) {
+namespace steps {
+
+int check_table_call(const double *pos, const double *mass, const double *eps, int64_t N, double L,
+                     const steps_cyl_table *t, int order, const int64_t *targets, int64_t n_targets,
+                     const float *out_acc) {
     if (!pos || !mass || !eps || !out_acc || !t)
         return fail(STEPS_EINVAL, "pos, mass, eps, out_acc and table must be non-null");
     if (N < 1 || N > STEPS_MAX_N) return fail(STEPS_EINVAL, "N=%lld outside [1, 2^29]", (long long)N);
@@ -398,11 +400,23 @@ STEPS_API int steps_cyl_forces_table(const double *pos, const double *mass, cons
     if (order != 1 && order != 2) return fail(STEPS_EINVAL, "order=%d: 1 (CIC) or 2 (TSC)", order);
     if (n_targets < 1 || n_targets > STEPS_MAX_N) return fail(STEPS_EINVAL, "n_targets out of range");
     if (!targets && n_targets != N) return fail(STEPS_EINVAL, "targets is NULL, so n_targets must equal N");
-    int rc = require_device();
-    if (rc) return rc;
-    clear_error();
+    return STEPS_OK;
+}
+
+size_t table_forces_bytes(int64_t N, const steps_cyl_table *t, int order, bool all_targets, int64_t n_targets,
+                          bool pot) {
+    return all_targets ? pairwise_bytes(N, 1, t, order, pot) : per_target_bytes(n_targets);
+}
+
+// The tabulated forces (arguments validated): the pairwise path for every
+// particle, the per-target kernel for a list.
+int launch_forces_table(const double *pos, const double *mass, const double *eps, int64_t N, double L,
+                        const steps_cyl_table *t, int order, const int64_t *targets, int64_t n_targets,
+                        float *out_acc, float *out_pot, Workspace &ws, hipStream_t stream) {
     // every particle a target: each unordered pair once
-    if (!targets) return launch_forces_pairwise(pos, mass, eps, N, L, 1, t, order, out_acc, out_pot, stream);
+    if (!targets) return launch_forces_pairwise(pos, mass, eps, N, L, 1, t, order, out_acc, out_pot, ws, stream);
+    int rc = check_workspace(ws, per_target_bytes(n_targets));
+    if (rc) return rc;
     TableArgs a;
     a.x = pos;
     a.y = pos + N;
@@ -419,16 +433,43 @@ STEPS_API int steps_cyl_forces_table(const double *pos, const double *mass, cons
     a.N = (int)N;
     a.n_tgt = (int)n_targets;
     a.perm = nullptr;
-    // walk the targets in spatial order (scratch is stream-ordered)
-    void *scratch = nullptr;
-    if (n_targets >= kOrderTargetsMin) {
-        if ((rc = order_targets(pos, N, L, targets, n_targets, stream, &scratch, &a.perm))) return rc;
-    }
+    // walk the targets in spatial order (keys and order in the workspace)
+    if (n_targets >= kOrderTargetsMin && (rc = order_targets(pos, N, L, targets, n_targets, stream, ws, &a.perm)))
+        return rc;
     hipError_t e;
     if (order == 1)
         e = out_pot ? launch_t<1, true>(a, stream) : launch_t<1, false>(a, stream);
     else
         e = out_pot ? launch_t<2, true>(a, stream) : launch_t<2, false>(a, stream);
-    if (scratch) (void)hipFreeAsync(scratch, stream);
     return hip_status(e, "forces_table launch");
+}
+
+}  // namespace steps
+
+STEPS_API int steps_cyl_forces_table_ws(const double *pos, const double *mass, const double *eps, int64_t N,
+                                        double L, const steps_cyl_table *t, int order, const int64_t *targets,
+                                        int64_t n_targets, float *out_acc, float *out_pot, void *workspace,
+                                        size_t workspace_bytes, hipStream_t stream) {
+    int rc = check_table_call(pos, mass, eps, N, L, t, order, targets, n_targets, out_acc);
+    if (rc) return rc;
+    if ((rc = require_device())) return rc;
+    clear_error();
+    Workspace ws;
+    ws.base = (char *)workspace;
+    ws.size = workspace ? workspace_bytes : 0;
+    return launch_forces_table(pos, mass, eps, N, L, t, order, targets, n_targets, out_acc, out_pot, ws, stream);
+}
+
+STEPS_API int steps_cyl_forces_table(const double *pos, const double *mass, const double *eps, int64_t N,
+                                     double L, const steps_cyl_table *t, int order, const int64_t *targets,
+                                     int64_t n_targets, float *out_acc, float *out_pot, hipStream_t stream) {
+    int rc = check_table_call(pos, mass, eps, N, L, t, order, targets, n_targets, out_acc);
+    if (rc) return rc;
+    if ((rc = require_device())) return rc;
+    clear_error();
+    const size_t bytes = table_forces_bytes(N, t, order, targets == nullptr, n_targets, out_pot != nullptr);
+    return with_stream_workspace(bytes, stream, [&](Workspace &ws) {
+        return launch_forces_table(pos, mass, eps, N, L, t, order, targets, n_targets, out_acc, out_pot, ws,
+                                   stream);
+    });
 }

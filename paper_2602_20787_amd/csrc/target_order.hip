@@ -51,36 +51,45 @@ __global__ void order_keys_kernel(const double *pos, int N, double L, const doub
 
 }  // namespace
 
+namespace {
+
+// bytes of rocPRIM's temporary storage for sorting n (key, index) pairs
+size_t sort_storage(int n) {
+    size_t bytes = 0;
+    if (rocprim::radix_sort_pairs(nullptr, bytes, (uint32_t *)nullptr, (uint32_t *)nullptr, (int *)nullptr,
+                                  (int *)nullptr, n, 0, 30) != hipSuccess)
+        return 0;
+    return bytes;
+}
+
+}  // namespace
+
+size_t order_targets_bytes(int64_t n_tgt) {
+    // partials; keys and indices, twice; the sort's storage
+    return ws_total({(size_t)8 * kExtentBlocks, (size_t)16 * n_tgt, sort_storage((int)n_tgt)});
+}
+
 int order_targets(const double *pos, int64_t N, double L, const int64_t *targets, int64_t n_tgt, hipStream_t stream,
-                  void **scratch, const int **perm) {
-    *scratch = nullptr;
+                  Workspace &ws, const int **perm) {
     *perm = nullptr;
     const int n = (int)n_tgt;
-    size_t cub = 0;
-    hipError_t e = rocprim::radix_sort_pairs(nullptr, cub, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                                      (int *)nullptr, (int *)nullptr, n, 0, 30, stream);
+    size_t sort_bytes = 0;
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, sort_bytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                             (int *)nullptr, (int *)nullptr, n, 0, 30, stream);
     if (e != hipSuccess) return hip_status(e, "target order");
-    // partials, keys and indices (twice), the sort's scratch
-    const size_t bytes = (size_t)8 * kExtentBlocks + (size_t)16 * n + 256 + cub;
-    if ((e = hipMallocAsync(scratch, bytes, stream)) != hipSuccess) {
-        *scratch = nullptr;
-        return fail(STEPS_ENOMEM, "target order scratch (%zu bytes)", bytes);
-    }
-    char *p = (char *)*scratch;
-    double *partial = (double *)p;
-    uint32_t *k_in = (uint32_t *)(p + 8 * kExtentBlocks), *k_out = k_in + n;
+    double *partial = (double *)ws.take((size_t)8 * kExtentBlocks);
+    uint32_t *k_in = (uint32_t *)ws.take((size_t)16 * n);
+    void *tmp = ws.take(sort_bytes);
+    if (!partial || !k_in || (sort_bytes && !tmp))
+        return fail(STEPS_EINVAL, "workspace too small for the target order (%zu bytes)", ws.size);
+    uint32_t *k_out = k_in + n;
     int *i_in = (int *)(k_out + n), *i_out = i_in + n;
-    void *tmp = (void *)(((uintptr_t)(i_out + n) + 255) & ~(uintptr_t)255);
     hipLaunchKernelGGL(extent_kernel, dim3(kExtentBlocks), dim3(256), 0, stream, pos, (int)N, partial);
     hipLaunchKernelGGL(order_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, pos, (int)N, L, partial,
                        targets, n, k_in, i_in);
     e = hipGetLastError();
-    if (e == hipSuccess) e = rocprim::radix_sort_pairs(tmp, cub, k_in, k_out, i_in, i_out, n, 0, 30, stream);
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(*scratch, stream);
-        *scratch = nullptr;
-        return hip_status(e, "target order");
-    }
+    if (e == hipSuccess) e = rocprim::radix_sort_pairs(tmp, sort_bytes, k_in, k_out, i_in, i_out, n, 0, 30, stream);
+    if (e != hipSuccess) return hip_status(e, "target order");
     *perm = i_out;
     return STEPS_OK;
 }

@@ -265,3 +265,38 @@ def test_tree_calls_reject_bad_arguments():
 def test_pairwise_mode_needs_every_particle():
     rc = sc.lib().steps_cyl_forces_ex(P, P, P, 10, 1.0, 8, P, 10, sc.STEPS_SUM_PAIRWISE, P, None, None)
     assert rc == sc.STEPS_EINVAL and "targets NULL" in sc.steps_cyl_last_error()
+
+
+def test_workspace_query_rejects_invalid_arguments():
+    L = sc.lib()
+    b = ctypes.c_size_t(123)
+    assert L.steps_cyl_forces_workspace(0, 10, 8, 0, 2, None, 0, 1, None) == sc.STEPS_EINVAL
+    assert "bytes" in sc.steps_cyl_last_error()
+    for args, msg in [((9, 10, 8, 0, 2, None, 0, 1), "path=9"),
+                      ((0, 0, 8, 0, 2, None, 0, 1), "N=0"),
+                      ((0, 2 ** 29 + 1, 8, 0, 2, None, 0, 1), "N="),
+                      ((0, 10, 8, -1, 2, None, 0, 1), "n_targets=-1"),
+                      ((0, 10, 4097, 0, 2, None, 0, 1), "n_img=4097"),
+                      ((0, 10, 8, 0, 7, None, 0, 1), "mode=7"),
+                      ((0, 10, 8, 5, 2, None, 0, 1), "STEPS_SUM_PAIRWISE"),
+                      ((1, 10, 8, 5, 2, None, 0, 1), "STEPS_SUM_PAIRWISE"),
+                      ((2, 10, 8, 0, 0, None, 1, 1), "table"),
+                      ((2, 10, 8, 0, 0, P, 3, 1), "order=3")]:
+        assert L.steps_cyl_forces_workspace(*args, ctypes.byref(b)) == sc.STEPS_EINVAL, args
+        assert msg in sc.steps_cyl_last_error(), (args, sc.steps_cyl_last_error())
+        assert b.value == 0
+
+
+@pytest.mark.parametrize("fn,args", [
+    ("steps_cyl_forces_ws", (None, P, P, 10, 1.0, 8, P, None, P, 64, None)),
+    ("steps_cyl_forces_ws", (P, P, P, 0, 1.0, 8, P, None, P, 64, None)),
+    ("steps_cyl_forces_ex_ws", (P, P, P, 10, 1.0, 8, None, 9, 0, P, None, P, 64, None)),
+    ("steps_cyl_forces_ex_ws", (P, P, P, 10, 1.0, 8, P, 3, 2, P, None, P, 64, None)),
+    ("steps_cyl_forces_f64_ws", (P, P, P, 10, 1.0, 8, P, 0, P, None, P, 64, None)),
+    ("steps_cyl_forces_learned_ws", (P, P, P, 10, 1.0, None, P, None, P, 64, None)),
+    ("steps_cyl_forces_learned_ex_ws", (P, P, P, 10, 1.0, P, P, 3, 5, P, None, P, 64, None)),
+    ("steps_cyl_forces_table_ws", (P, P, P, 10, 1.0, P, 3, None, 10, P, None, P, 64, None)),
+])
+def test_workspace_entry_points_reject_invalid_arguments(fn, args):
+    # validated on the host before the device check and any use of the workspace
+    assert getattr(sc.lib(), fn)(*args) == sc.STEPS_EINVAL

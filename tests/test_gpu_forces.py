@@ -234,6 +234,43 @@ def test_config3_full_size_sampled_and_momentum(sc):
     assert mom.max() <= 1e-5 * scale
 
 
+@pytest.mark.timeout(600)
+def test_config3_precision_study(sc):
+    # C3 at full size: FP32 pair terms with Kahan-compensated per-target sums,
+    # with plain FP32 per-target sums, and the pairwise path (FP64 sums)
+    # against the FP64 GPU reference on 8192 targets; the reference itself
+    # against the CPU oracle on 64 of them.  The bar is the exact path's 1e-5
+    # for the compensated and the pairwise sums; plain FP32 sums over 2^20
+    # sources are the study's contrast (reported, bounded loosely).
+    p = synth.cylinder_load(1 << 20, seed=0)
+    pos, m, e = to_dev(p)
+    tg = synth.target_sample(p.N, 8192, seed=31)
+    t = torch.from_numpy(tg).cuda()
+    print("[case] C3 precision study, N=2^20, 8192 targets", flush=True)
+    ref, ref_pot = sc.steps_cyl_forces_f64(pos, m, e, p.L, 8, targets=t)
+    comp, comp_pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t, mode=sc.STEPS_SUM_COMPENSATED)
+    plain, plain_pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t, mode=sc.STEPS_SUM_PLAIN)
+    full, full_pot = sc.steps_cyl_forces(pos, m, e, p.L, 8)
+    torch.cuda.synchronize()
+    r, rp = ref.cpu().numpy(), ref_pot.cpu().numpy()
+    rows = {"compensated": (comp, comp_pot), "plain": (plain, plain_pot), "pairwise": (full[:, t], full_pot[t])}
+    err = {}
+    for k, (a, ap) in rows.items():
+        ea = rel_err(a, r)
+        ep = pot_err(ap, rp)
+        err[k] = (ea, ep)
+        print(f"{k:12s} max {ea.max():.3e} rms {math.sqrt(np.mean(ea ** 2)):.3e} "
+              f"p99.9 {np.percentile(ea, 99.9):.3e} potential max {ep.max():.3e}")
+    assert err["compensated"][0].max() <= TOL_ACC and err["compensated"][1].max() <= TOL_POT
+    assert err["pairwise"][0].max() <= TOL_ACC and err["pairwise"][1].max() <= TOL_POT
+    assert err["plain"][0].max() <= 1e-2
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8, targets=tg[:64])
+    eo = np.linalg.norm(r[:, :64] - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)
+    print(f"FP64 reference vs oracle (64 targets): max {eo.max():.3e}")
+    assert eo.max() <= 1e-11
+    assert (np.abs(rp[:64] - p_ref) / np.abs(p_ref)).max() <= 1e-12
+
+
 def test_all_targets_in_spatial_order_are_bitwise_the_subset_results(sc):
     # a call over all targets walks them in spatial order; each target's sum
     # is unchanged, so it equals bit for bit the same targets asked for by index

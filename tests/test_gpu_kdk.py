@@ -168,3 +168,32 @@ def test_step_on_tabulated_history_matches_oracle(sc):
     assert np.abs(dx).max() <= 2e-5 * kick * fac[1] + 1e-14
     # and the table reproduces the Friedmann step it was sampled from
     np.testing.assert_allclose(fac, bg.kdk_factors(0.05, 0.06, c), rtol=1e-6)
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_steps_are_bitwise_reproducible(sc, learned):
+    # the force paths follow a fixed schedule with no atomics and the kick and
+    # drift are elementwise, so two runs of the same steps agree bit for bit
+    import os
+    NET = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2602_20787_amd", "data", "correction_net.bin")
+    net = sc.Mlp.load(NET) if learned else None
+    p = synth.displaced_load(5000, seed=7)
+    c, R, rho0 = cosmo_for_load()
+    out = []
+    for _ in range(2):
+        pos, mom, m, e, _ = _state(sc, p)
+        if learned:
+            acc, _ = sc.steps_cyl_forces_learned(pos, m, e, p.L, net, potential=False)
+        else:
+            acc, _ = sc.steps_cyl_forces(pos, m, e, p.L, 8, potential=False)
+        a_grid = np.exp(np.linspace(math.log(0.02), math.log(0.03), 4))
+        for a0, a1 in zip(a_grid[:-1], a_grid[1:]):
+            par = sc.kdk_params(a0, a1, c.H0, c.Om, c.OL, R_cyl=R, rho0=rho0, n_img=8, net=net)
+            sc.steps_cyl_kdk_step(pos, mom, m, e, p.L, par, acc)
+        torch.cuda.synchronize()
+        out.append((pos.clone(), mom.clone(), acc.clone()))
+    for x, y in zip(out[0], out[1]):
+        assert torch.equal(x, y)
+    if net is not None:
+        net.close()

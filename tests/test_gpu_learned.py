@@ -120,6 +120,20 @@ def test_pairwise_learned_matches_per_target_and_oracle(sc, net, N):
     assert mom.max() <= 1e-5
 
 
+@pytest.mark.parametrize("N", [5000, 9000])
+def test_pairwise_learned_is_deterministic(sc, net, N):
+    # a fixed tournament of groups (even and odd group counts), no atomics:
+    # repeated calls are bitwise equal (a race in the reactions' LDS sums or
+    # in the read-modify-writes of the sums would show up here)
+    p = load_with_axis_line(N, seed=90 + N)
+    pos, m, e = to_dev(p)
+    print(f"[case] pairwise learned determinism N={N}", flush=True)
+    a1, p1 = sc.steps_cyl_forces_learned(pos, m, e, p.L, net)
+    a2, p2 = sc.steps_cyl_forces_learned(pos, m, e, p.L, net)
+    torch.cuda.synchronize()
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+
+
 def test_learned_ragged_and_plain(sc, net):
     p = load_with_axis_line(333, seed=33)
     pos, m, e = to_dev(p)

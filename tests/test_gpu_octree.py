@@ -170,9 +170,13 @@ def test_force_error_statistics_follow_the_opening_angle(sc):
     err = [r[2] for r in rows]
     assert all(a < b for a, b in zip(err[:-1], err[1:]))
     assert err[1] < 1e-2
-    # the correction brings the mean radial ratio closer to one
-    for r in rows[1:]:
-        assert abs(r[6] - 1) <= abs(r[3] - 1) + 1e-4
+    # the correction, calibrated on 4 other random frames, removes the
+    # systematic radial bias: where the raw bias stands above the spread of a
+    # single frame's mean radial ratio (about 3e-4 on this load) it brings the
+    # ratio closer to one, and elsewhere it leaves it within that spread
+    for r in rows:
+        assert abs(r[6] - 1) <= max(abs(r[3] - 1), 3e-4)
+    assert abs(rows[2][6] - 1) < 0.6 * abs(rows[2][3] - 1)  # theta = 0.7: a clear bias, clearly reduced
     tab.close()
 
 

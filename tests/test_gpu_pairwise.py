@@ -107,14 +107,22 @@ def test_axial_separation_of_half_a_period(sc):
 
 
 def test_matches_the_one_sided_kernel_and_conserves_momentum(sc):
+    # every target of a 2^16 load: both paths against the FP64 GPU reference
+    # (itself pinned to the oracle in test_gpu_forces) at the exact path's
+    # bar, and against each other within the sum of their errors
     p = synth.cylinder_load(1 << 16, seed=4)
     pos, m, e = dev(p.pos), dev(p.mass), dev(p.eps)
     a1, p1 = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8)
     a2, p2 = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, mode=sc.STEPS_SUM_PAIRWISE)
+    ref, ref_pot = sc.steps_cyl_forces_f64(pos, m, e, p.L, 8)
     torch.cuda.synchronize()
-    a1, a2 = a1.double().cpu().numpy(), a2.double().cpu().numpy()
-    assert rel(a2, a1).max() <= 2e-6
-    assert (torch.abs(p2.double() - p1.double()) / torch.abs(p1.double())).max().item() <= 2e-6
+    a1, a2, r = a1.double().cpu().numpy(), a2.double().cpu().numpy(), ref.cpu().numpy()
+    e1, e2 = rel(a1, r), rel(a2, r)
+    print(f"vs FP64 on all targets: one-sided max {e1.max():.2e}, pairwise max {e2.max():.2e}")
+    assert e1.max() <= TOL and e2.max() <= TOL
+    assert rel(a2, a1).max() <= e1.max() + e2.max()
+    for pt in (p1, p2):
+        assert (torch.abs(pt.double() - ref_pot) / torch.abs(ref_pot)).max().item() <= TOL
     mom = np.abs((p.mass[None, :] * a2).sum(axis=1)) / (p.mass[None, :] * np.abs(a2)).sum(axis=1)
     mom1 = np.abs((p.mass[None, :] * a1).sum(axis=1)) / (p.mass[None, :] * np.abs(a1)).sum(axis=1)
     print("momentum residual pairwise", mom, "one-sided", mom1)
