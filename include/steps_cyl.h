@@ -43,6 +43,14 @@
  *    and every target's result is bitwise that of the unsorted walk.  The
  *    keys (about 16 bytes per target plus the radix sort's storage) live in
  *    the workspace.
+ *  - Short target lists: when a per-target call's target blocks alone would
+ *    not fill the device, the sources are split into C chunks of at least
+ *    4096 (C = min(ceil(2048 / target blocks), ceil(N / 4096)), target blocks
+ *    of 256 targets, 128 with a network); each chunk's compensated totals go
+ *    to the workspace in FP64 (32 C bytes per target) and are added in chunk
+ *    order.  Results are deterministic, and two calls on the same particles
+ *    give a target bit for bit the same result whenever they take the same
+ *    C (always for N <= 4096); otherwise they agree to FP32 rounding.
  *  - Every call is asynchronous on `stream` (0 = the null stream); results
  *    are valid after the stream is synchronised.  Argument errors are found
  *    on the host before any device work and return a negative status; the

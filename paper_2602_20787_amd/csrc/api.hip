@@ -16,6 +16,8 @@ int launch_forces_learned(const double *pos, const double *mass, const double *e
                           float *out_acc, float *out_pot, Workspace &ws, hipStream_t stream);
 size_t table_forces_bytes(int64_t N, const steps_cyl_table *t, int order, bool all_targets, int64_t n_targets,
                           bool pot);
+size_t exact_per_target_bytes(int64_t N, int64_t n_tgt);
+size_t learned_per_target_bytes(int64_t N, int64_t n_tgt);
 
 namespace {
 
@@ -52,7 +54,7 @@ Workspace caller_workspace(void *p, size_t bytes) {
 // the exact path of steps_cyl_forces_ex (validated arguments)
 size_t exact_bytes(int64_t N, int n_img, bool all_targets, int64_t n_targets, int mode, bool pot) {
     if (mode == STEPS_SUM_PAIRWISE) return pairwise_bytes(N, n_img, nullptr, 0, pot);
-    return per_target_bytes(all_targets ? N : n_targets);
+    return exact_per_target_bytes(N, all_targets ? N : n_targets);
 }
 
 int run_exact(const double *pos, const double *mass, const double *eps, int64_t N, double L, int n_img,
@@ -66,7 +68,7 @@ int run_exact(const double *pos, const double *mass, const double *eps, int64_t 
 
 size_t learned_bytes(int64_t N, bool all_targets, int64_t n_targets, int mode) {
     if (mode == STEPS_SUM_PAIRWISE) return learned_pairwise_bytes(N);
-    return per_target_bytes(all_targets ? N : n_targets);
+    return learned_per_target_bytes(N, all_targets ? N : n_targets);
 }
 
 int run_learned(const double *pos, const double *mass, const double *eps, int64_t N, double L,

@@ -29,6 +29,15 @@
 // Accumulation.  Per target, FP32 partial sums over 32 sources are folded
 // into Kahan-compensated totals (or, in plain mode, every pair is added
 // straight into an FP32 total).
+//
+// Short target lists.  When the target blocks alone would leave the device
+// idle, the sources are split into chunks too (a grid of target blocks x
+// source chunks): each workgroup writes its compensated totals in FP64 to
+// the workspace and a second pass adds the chunks in order.  The chunking
+// depends only on the list's length and N, so results stay deterministic;
+// lists long enough to fill the device take one chunk and the direct write.
+#include <algorithm>
+
 #include "common.h"
 #include "pair_f64.h"
 #include "pair_fp32.h"
@@ -45,9 +54,11 @@ struct ExactArgs {
     const int64_t *targets;  // null: target k is particle k
     const int *perm;         // list positions in spatial order of their targets, or null
     float *ax, *ay, *az, *pot;
+    double *part;            // [chunks][4][n_tgt] chunk totals, or null for one chunk
     double L, invL, halfL;
     ImageConsts c;
     int N, n_tgt;
+    int chunk;               // sources per chunk (a multiple of kBlock, or N)
 };
 
 template <int NIMG, bool POT, bool COMP>
@@ -65,10 +76,11 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
     float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;  // Kahan compensations
 
     __shared__ float wave_hmax[kBlock / 64];
-    for (int base = 0; base < a.N; base += kBlock) {
+    const int j0 = blockIdx.y * a.chunk, j1 = min(a.N, j0 + a.chunk);
+    for (int base = j0; base < j1; base += kBlock) {
         const int j = base + tid;
         float hj = 0.f;
-        if (j < a.N) {
+        if (j < j1) {
             SrcRec r;
             r.x = a.x[j];
             r.y = a.y[j];
@@ -88,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
         const float hb = hi + hmax;        // >= h_i + h_j for every source in the tile
         const float thr2 = hb * hb;        // rounding is monotonic: >= (h_i + h_j)^2
         const bool wide = hb > (float)a.halfL;
-        const int cnt = min(kBlock, a.N - base);
+        const int cnt = min(kBlock, j1 - base);
         for (int s0 = 0; s0 < cnt; s0 += kSub) {
             const int e = min(kSub, cnt - s0);
             float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f;
@@ -142,17 +154,41 @@ __global__ __launch_bounds__(kBlock) void forces_exact_kernel(ExactArgs a) {
     if (active) {
         // attraction: a = -sum m_j S (x_i - x_j), potential = -sum m_j / r
         const int64_t o = kk;
-        a.ax[o] = -(sx - cx);
-        a.ay[o] = -(sy - cy);
-        a.az[o] = -(sz - cz);
-        if (POT) a.pot[o] = -(sp - cp);
+        if (a.part) {
+            double *q = a.part + (int64_t)blockIdx.y * 4 * a.n_tgt + o;
+            q[0] = (double)sx - (double)cx;
+            q[a.n_tgt] = (double)sy - (double)cy;
+            q[2 * (int64_t)a.n_tgt] = (double)sz - (double)cz;
+            q[3 * (int64_t)a.n_tgt] = (double)sp - (double)cp;
+        } else {
+            a.ax[o] = -(sx - cx);
+            a.ay[o] = -(sy - cy);
+            a.az[o] = -(sz - cz);
+            if (POT) a.pot[o] = -(sp - cp);
+        }
     }
+}
+
+// Chunk totals of a short target list added in chunk order (FP64), negated
+// and written as FP32.
+__global__ void exact_chunks_kernel(const double *part, int chunks, int n_tgt, float *ax, float *ay, float *az,
+                                    float *pot) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_tgt) return;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < chunks; ++c)
+        for (int q = 0; q < 4; ++q) v[q] += part[((int64_t)c * 4 + q) * n_tgt + k];
+    ax[k] = (float)(-v[0]);
+    ay[k] = (float)(-v[1]);
+    az[k] = (float)(-v[2]);
+    if (pot) pot[k] = (float)(-v[3]);
 }
 
 template <int NIMG, bool POT, bool COMP>
 hipError_t launch_t(const ExactArgs &a, hipStream_t stream) {
     const int grid = (a.n_tgt + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL((forces_exact_kernel<NIMG, POT, COMP>), dim3(grid), dim3(kBlock), 0, stream, a);
+    const int chunks = (a.N + a.chunk - 1) / a.chunk;
+    hipLaunchKernelGGL((forces_exact_kernel<NIMG, POT, COMP>), dim3(grid, chunks), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -169,6 +205,23 @@ hipError_t launch_nimg(const ExactArgs &a, hipStream_t stream) {
 }
 
 }  // namespace
+
+// Source chunks of the per-target kernels for n_tgt targets of N sources:
+// enough (target block, chunk) pairs for 2048 workgroups, chunks of at least
+// 4096 sources; one chunk once the targets fill the device.
+int per_target_chunks(int64_t N, int64_t n_tgt, int block) {
+    const int64_t tblocks = (n_tgt + block - 1) / block;
+    int64_t c = (2048 + tblocks - 1) / tblocks;
+    c = std::min<int64_t>(c, (N + 4095) / 4096);
+    return (int)std::max<int64_t>(1, c);
+}
+
+// Workspace of the per-target exact kernel: the spatial order of a long
+// list, and the chunk totals of a short one.
+size_t exact_per_target_bytes(int64_t N, int64_t n_tgt) {
+    const int chunks = per_target_chunks(N, n_tgt, kBlock);
+    return ws_total({per_target_bytes(n_tgt), chunks > 1 ? (size_t)chunks * 4 * n_tgt * sizeof(double) : 0});
+}
 
 // Launches the FP32 exact-force kernel; arguments already validated.
 int launch_forces_exact(const double *pos, const double *mass, const double *eps, int64_t N,
@@ -196,16 +249,30 @@ int launch_forces_exact(const double *pos, const double *mass, const double *eps
     a.n_tgt = (int)n_tgt;
     a.perm = nullptr;
     // walk the targets in spatial order (keys and order in the workspace)
-    int rc = check_workspace(ws, per_target_bytes(n_tgt));
+    int rc = check_workspace(ws, exact_per_target_bytes(N, n_tgt));
     if (rc) return rc;
     if (n_tgt >= kOrderTargetsMin && (rc = order_targets(pos, N, L, targets, n_tgt, stream, ws, &a.perm)))
         return rc;
+    const int chunks = per_target_chunks(N, n_tgt, kBlock);
+    a.chunk = (int)N;
+    a.part = nullptr;
+    if (chunks > 1) {
+        a.chunk = (int)(((N + chunks - 1) / chunks + kBlock - 1) / kBlock * kBlock);
+        a.part = (double *)ws.take((size_t)chunks * 4 * n_tgt * sizeof(double));
+        if (!a.part) return fail(STEPS_EINVAL, "workspace too small for the chunk totals");
+    }
     hipError_t e;
     const bool comp = (mode == STEPS_SUM_COMPENSATED);
     if (out_pot)
         e = comp ? launch_nimg<true, true>(a, stream) : launch_nimg<true, false>(a, stream);
     else
         e = comp ? launch_nimg<false, true>(a, stream) : launch_nimg<false, false>(a, stream);
+    if (e == hipSuccess && a.part) {
+        const int nch = (int)((N + a.chunk - 1) / a.chunk);
+        hipLaunchKernelGGL(exact_chunks_kernel, dim3((unsigned)((n_tgt + 255) / 256)), dim3(256), 0, stream, a.part,
+                           nch, (int)n_tgt, out_acc, out_acc + n_tgt, out_acc + 2 * n_tgt, out_pot);
+        e = hipGetLastError();
+    }
     return hip_status(e, "forces_exact launch");
 }
 

@@ -38,10 +38,12 @@ struct LearnedArgs {
     const int *perm;  // list positions in spatial order of their targets, or null
     const mlp::Packed *P;
     float *ax, *ay, *az, *pot;
+    double *part;     // [chunks][4][n_tgt] chunk totals of a short list, or null
     double L, invL, halfL;
     float invLf, invL2f;
     ImageConsts c;  // n_img = 1
     int N, n_tgt;
+    int chunk;        // sources per chunk (a multiple of kTile, or N)
 };
 
 // Exact band 2 <= |n| <= 1024 for one pair (delta = d/L signed, r = rho/L),
@@ -138,10 +140,11 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
     float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;
     float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
 
-    for (int base = 0; base < a.N; base += kTile) {
+    const int j0 = blockIdx.y * a.chunk, j1 = min(a.N, j0 + a.chunk);
+    for (int base = j0; base < j1; base += kTile) {
         __syncthreads();
         const int j = base + tid;
-        if (j < a.N) {
+        if (j < j1) {
             SrcRec r;
             r.x = a.x[j];
             r.y = a.y[j];
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
             tile[tid] = r;
         }
         __syncthreads();
-        const int cnt = min(kTile, a.N - base);
+        const int cnt = min(kTile, j1 - base);
         for (int s0 = 0; s0 < cnt; s0 += kSub) {
             const int e = min(kSub, cnt - s0);
             float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f;
@@ -225,17 +228,41 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
     const float oz = __shfl_xor(sz - cz, 32), op = __shfl_xor(sp - cp, 32);
     if (active && h == 0) {
         const int64_t o = kk;
-        a.ax[o] = -((sx - cx) + ox);
-        a.ay[o] = -((sy - cy) + oy);
-        a.az[o] = -((sz - cz) + oz);
-        if (POT) a.pot[o] = -((sp - cp) + op);
+        if (a.part) {
+            double *q = a.part + (int64_t)blockIdx.y * 4 * a.n_tgt + o;
+            q[0] = (double)(sx - cx) + (double)ox;
+            q[a.n_tgt] = (double)(sy - cy) + (double)oy;
+            q[2 * (int64_t)a.n_tgt] = (double)(sz - cz) + (double)oz;
+            q[3 * (int64_t)a.n_tgt] = (double)(sp - cp) + (double)op;
+        } else {
+            a.ax[o] = -((sx - cx) + ox);
+            a.ay[o] = -((sy - cy) + oy);
+            a.az[o] = -((sz - cz) + oz);
+            if (POT) a.pot[o] = -((sp - cp) + op);
+        }
     }
+}
+
+// Chunk totals of a short target list added in chunk order (FP64), negated
+// and written as FP32.
+__global__ void learned_chunks_kernel(const double *part, int chunks, int n_tgt, float *ax, float *ay, float *az,
+                                      float *pot) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_tgt) return;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < chunks; ++c)
+        for (int q = 0; q < 4; ++q) v[q] += part[((int64_t)c * 4 + q) * n_tgt + k];
+    ax[k] = (float)(-v[0]);
+    ay[k] = (float)(-v[1]);
+    az[k] = (float)(-v[2]);
+    if (pot) pot[k] = (float)(-v[3]);
 }
 
 template <bool POT, bool COMP>
 hipError_t launch_t(const LearnedArgs &a, hipStream_t stream) {
     const int grid = (a.n_tgt + kTargets - 1) / kTargets;
-    hipLaunchKernelGGL((forces_learned_kernel<POT, COMP>), dim3(grid), dim3(kBlock), 0, stream, a);
+    const int chunks = (a.N + a.chunk - 1) / a.chunk;
+    hipLaunchKernelGGL((forces_learned_kernel<POT, COMP>), dim3(grid, chunks), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -243,6 +270,16 @@ hipError_t launch_t(const LearnedArgs &a, hipStream_t stream) {
 
 namespace mlp {
 const Packed *packed_of(const steps_cyl_mlp *net);
+}
+
+int per_target_chunks(int64_t N, int64_t n_tgt, int block);
+
+// Workspace of the per-target learned kernel: the spatial order of a long
+// list and the chunk totals of a short one (sources split into chunks when
+// the target blocks alone would leave the device idle; see forces_exact.hip).
+size_t learned_per_target_bytes(int64_t N, int64_t n_tgt) {
+    const int chunks = per_target_chunks(N, n_tgt, kTargets);
+    return ws_total({per_target_bytes(n_tgt), chunks > 1 ? (size_t)chunks * 4 * n_tgt * sizeof(double) : 0});
 }
 
 int launch_forces_learned(const double *pos, const double *mass, const double *eps, int64_t N, double L,
@@ -273,16 +310,30 @@ int launch_forces_learned(const double *pos, const double *mass, const double *e
     a.n_tgt = (int)n_tgt;
     a.perm = nullptr;
     // walk the targets in spatial order (keys and order in the workspace)
-    int rc = check_workspace(ws, per_target_bytes(n_tgt));
+    int rc = check_workspace(ws, learned_per_target_bytes(N, n_tgt));
     if (rc) return rc;
     if (n_tgt >= kOrderTargetsMin && (rc = order_targets(pos, N, L, targets, n_tgt, stream, ws, &a.perm)))
         return rc;
+    const int chunks = per_target_chunks(N, n_tgt, kTargets);
+    a.chunk = (int)N;
+    a.part = nullptr;
+    if (chunks > 1) {
+        a.chunk = (int)(((N + chunks - 1) / chunks + kTile - 1) / kTile * kTile);
+        a.part = (double *)ws.take((size_t)chunks * 4 * n_tgt * sizeof(double));
+        if (!a.part) return fail(STEPS_EINVAL, "workspace too small for the chunk totals");
+    }
     const bool comp = (mode == STEPS_SUM_COMPENSATED);
     hipError_t e;
     if (out_pot)
         e = comp ? launch_t<true, true>(a, stream) : launch_t<true, false>(a, stream);
     else
         e = comp ? launch_t<false, true>(a, stream) : launch_t<false, false>(a, stream);
+    if (e == hipSuccess && a.part) {
+        const int nch = (int)((N + a.chunk - 1) / a.chunk);
+        hipLaunchKernelGGL(learned_chunks_kernel, dim3((unsigned)((n_tgt + 255) / 256)), dim3(256), 0, stream,
+                           a.part, nch, (int)n_tgt, out_acc, out_acc + n_tgt, out_acc + 2 * n_tgt, out_pot);
+        e = hipGetLastError();
+    }
     return hip_status(e, "forces_learned launch");
 }
 
@@ -315,7 +366,7 @@ int launch_forces_learned(const double *pos, const double *mass, const double *e
 namespace {
 
 constexpr int kOwn = 128;  // particles per sub-group, one per wave column
-constexpr int kSubs = 4;   // sub-groups per group
+constexpr int kSubs = 8;   // sub-groups per group
 constexpr int kSlots = 2 * kSubs;  // sums per particle: actions by source sub-group, reactions by target sub-group
 
 struct PairwiseLearnedArgs {

@@ -296,3 +296,24 @@ def test_long_target_lists_in_spatial_order_are_bitwise_exact(sc):
     torch.cuda.synchronize()
     assert torch.equal(full[:, tg], sub)
     assert torch.equal(fpot[tg], spot)
+
+
+@pytest.mark.parametrize("mode", ["compensated", "plain"])
+def test_short_lists_split_the_sources_into_chunks(sc, mode):
+    # 500 targets of 2^17 sources: 2 target blocks, so the sources are split
+    # into 32 chunks whose totals are added in order; against the oracle
+    p = synth.cylinder_load(1 << 17, seed=13)
+    pos, m, e = to_dev(p)
+    tg = synth.target_sample(p.N, 500, seed=14)
+    t = torch.from_numpy(tg).cuda()
+    md = sc.STEPS_SUM_COMPENSATED if mode == "compensated" else sc.STEPS_SUM_PLAIN
+    print(f"[case] chunked per-target N=2^17, 500 targets, {mode}", flush=True)
+    acc, pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t, mode=md)
+    acc2, pot2 = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t, mode=md)
+    torch.cuda.synchronize()
+    assert torch.equal(acc, acc2) and torch.equal(pot, pot2)
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8, targets=tg[:120])
+    err = rel_err(acc[:, :120], a_ref)
+    print(f"chunked {mode}: max {err.max():.3e}")
+    assert err.max() <= (TOL_ACC if mode == "compensated" else 1e-4)
+    assert pot_err(pot[:120], p_ref).max() <= TOL_POT

@@ -134,6 +134,21 @@ def test_pairwise_learned_is_deterministic(sc, net, N):
     assert torch.equal(a1, a2) and torch.equal(p1, p2)
 
 
+def test_short_lists_split_the_sources_into_chunks(sc, net):
+    # 300 targets of 20,000 sources: 3 target blocks, so the sources are
+    # split into 5 chunks whose totals are added in order
+    p = load_with_axis_line(20000, seed=95)
+    pos, m, e = to_dev(p)
+    tg = np.unique(np.concatenate([np.arange(16), synth.target_sample(p.N, 284, seed=96)]))
+    t = torch.from_numpy(tg).cuda()
+    print("[case] chunked learned per-target", flush=True)
+    acc, _ = sc.steps_cyl_forces_learned_ex(pos, m, e, p.L, net, targets=t, potential=False)
+    torch.cuda.synchronize()
+    sub = tg[:40]
+    ref = om.forces_learned(p.pos, p.mass, p.eps, p.L, net.params().astype(np.float64), targets=sub)
+    assert rel_err(acc[:, :40], ref).max() <= TOL
+
+
 def test_learned_ragged_and_plain(sc, net):
     p = load_with_axis_line(333, seed=33)
     pos, m, e = to_dev(p)

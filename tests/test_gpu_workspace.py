@@ -94,10 +94,11 @@ def test_per_target_and_f64_in_a_workspace(sc, pool, n_targets):
     pos, m, e = to_dev(p)
     t = torch.from_numpy(synth.target_sample(p.N, n_targets, seed=4)).cuda()
     nb = sc.steps_cyl_forces_workspace(sc.STEPS_PATH_EXACT, p.N, 8, n_targets, sc.STEPS_SUM_COMPENSATED)
-    # lists of 4096 or more are ordered in the workspace; shorter ones need none
-    assert (nb > 0) == (n_targets >= 4096)
+    # lists of 4096 or more are ordered in the workspace, and these short
+    # lists split the 9000 sources into chunks whose totals it holds
+    assert nb >= 3 * 32 * n_targets
     ref = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=t)
-    ws = workspace(max(nb, 1))
+    ws = workspace(nb)
     pool.reset()
     out = sc.steps_cyl_forces_ex_ws(pos, m, e, p.L, 8, ws, targets=t)
     assert pool.high() == 0
