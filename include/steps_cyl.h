@@ -165,6 +165,30 @@ int steps_cyl_forces_ws(const double *pos, const double *mass, const double *eps
                         void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * steps_cyl_forces_noalloc -- steps_cyl_forces for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same pairwise path and arguments,
+ * with its workspace in a fixed 96 MiB array of the library's device image
+ * instead of per-call memory.  Each device the library runs on holds its own
+ * copy of the array until the process ends.  Calls no allocator.
+ *
+ *   N   1 <= N <= STEPS_NOALLOC_MAX_N (2^20); larger N return STEPS_EINVAL
+ *       with a message naming the limit, before any device work
+ *
+ * The workgroups per meeting are the device's choice or fewer, so that the
+ * workspace fits the array; where they are fewer the sums run in another
+ * (fixed) order than in steps_cyl_forces and the results agree with it to
+ * FP32 rounding, otherwise bit for bit.  Every call on a device shares that
+ * device's array and finds it as the last call left it (nothing in it needs
+ * to start at zero): calls that overlap on one device, on different streams
+ * or from different threads, race and give undefined results.
+ */
+#define STEPS_NOALLOC_MAX_N (1LL << 20)
+int steps_cyl_forces_noalloc(const double *pos, const double *mass, const double *eps,
+                             int64_t N, double L, int n_img,
+                             float *out_acc, float *out_pot, hipStream_t stream);
+
+/*
  * steps_cyl_forces_ex -- as steps_cyl_forces, for a subset of targets and a
  * chosen summation mode.  Sources are always all N particles.
  *

@@ -14,6 +14,7 @@ import os
 __all__ = [
     "StepsError", "lib", "library_path",
     "steps_cyl_forces", "steps_cyl_forces_ex", "steps_cyl_forces_f64",
+    "steps_cyl_forces_noalloc", "STEPS_NOALLOC_MAX_N",
     "steps_cyl_forces_workspace", "steps_cyl_forces_ws", "steps_cyl_forces_ex_ws", "steps_cyl_forces_f64_ws",
     "steps_cyl_forces_learned_ws", "steps_cyl_forces_learned_ex_ws", "steps_cyl_forces_table_ws",
     "STEPS_PATH_EXACT", "STEPS_PATH_LEARNED", "STEPS_PATH_TABLE", "STEPS_PATH_F64",
@@ -50,6 +51,7 @@ STEPS_SUM_PAIRWISE = 2
 STEPS_MAX_NIMG = 4096
 STEPS_MAX_N = 1 << 29
 STEPS_MLP_PARAMS = 12802
+STEPS_NOALLOC_MAX_N = 1 << 20
 STEPS_PATH_EXACT = 0
 STEPS_PATH_LEARNED = 1
 STEPS_PATH_TABLE = 2
@@ -131,6 +133,7 @@ _SIGNATURES = {
     "steps_cyl_tree_info": [_VP, _VP, _VP, _VP],
     "steps_cyl_tree_cells": [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
     "steps_cyl_forces_table": [_VP, _VP, _VP, _I64, _F64, _VP, _I32, _VP, _I64, _VP, _VP, _VP],
+    "steps_cyl_forces_noalloc": [_VP, _VP, _VP, _I64, _F64, _I32, _VP, _VP, _VP],
     "steps_cyl_forces_workspace": [_I32, _I64, _I32, _I64, _I32, _VP, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)],
     "steps_cyl_forces_ws": [_VP, _VP, _VP, _I64, _F64, _I32, _VP, _VP, _VP, _SZ, _VP],
     "steps_cyl_forces_ex_ws": [_VP, _VP, _VP, _I64, _F64, _I32, _VP, _I64, _I32, _VP, _VP, _VP, _SZ, _VP],
@@ -255,6 +258,24 @@ def steps_cyl_forces(pos, mass, eps, L, n_img, out_acc=None, out_pot=None, poten
     p_pot = _dev(out_pot, torch.float32, "out_pot", N) if potential else None
     _call("steps_cyl_forces", (p_pos, p_m, p_e, N, float(L), int(n_img), p_acc, p_pot),
           _stream(stream, pos.device), workspace)
+    return out_acc, (out_pot if potential else None)
+
+
+def steps_cyl_forces_noalloc(pos, mass, eps, L, n_img, out_acc=None, out_pot=None, potential=True,
+                             stream=None):
+    """:func:`steps_cyl_forces` in the library's static device scratch (no
+    allocation by the library; N <= STEPS_NOALLOC_MAX_N; calls on one device
+    must not overlap)."""
+    import torch
+    N, p_pos, p_m, p_e = _sources(pos, mass, eps)
+    if out_acc is None:
+        out_acc = torch.empty((3, N), dtype=torch.float32, device=pos.device)
+    if potential and out_pot is None:
+        out_pot = torch.empty((N,), dtype=torch.float32, device=pos.device)
+    p_acc = _dev(out_acc, torch.float32, "out_acc", 3 * N)
+    p_pot = _dev(out_pot, torch.float32, "out_pot", N) if potential else None
+    _check(lib().steps_cyl_forces_noalloc(p_pos, p_m, p_e, N, float(L), int(n_img), p_acc, p_pot,
+                                          _stream(stream, pos.device)))
     return out_acc, (out_pot if potential else None)
 
 

@@ -300,3 +300,13 @@ def test_workspace_query_rejects_invalid_arguments():
 def test_workspace_entry_points_reject_invalid_arguments(fn, args):
     # validated on the host before the device check and any use of the workspace
     assert getattr(sc.lib(), fn)(*args) == sc.STEPS_EINVAL
+
+
+def test_noalloc_rejects_sizes_beyond_its_static_scratch():
+    # checked on the host before the device check: N above STEPS_NOALLOC_MAX_N
+    L = sc.lib()
+    assert sc.STEPS_NOALLOC_MAX_N == 2 ** 20
+    assert L.steps_cyl_forces_noalloc(P, P, P, 2 ** 20 + 1, 1.0, 8, P, None, None) == sc.STEPS_EINVAL
+    assert "static scratch" in sc.steps_cyl_last_error()
+    assert L.steps_cyl_forces_noalloc(P, P, P, 0, 1.0, 8, P, None, None) == sc.STEPS_EINVAL
+    assert L.steps_cyl_forces_noalloc(None, P, P, 10, 1.0, 8, P, None, None) == sc.STEPS_EINVAL

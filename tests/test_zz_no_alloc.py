@@ -1,0 +1,64 @@
+"""steps_cyl_forces_noalloc, the entry point for callers that cannot
+allocate: called through the C ABI with caller-owned inputs and outputs only,
+its results match steps_cyl_forces (same kernels, workspace in the library's
+static device array) on two calls in a row, the second with a smaller input
+than the first, so that the second finds the array as the first left it.
+
+Bar: the exact path's 1e-5 relative acceleration and potential error against
+steps_cyl_forces (both are FP32 pair terms with FP64 sums).  At N = 300,000
+the static array holds fewer workgroups per meeting than the device would
+take, so the sums run in another fixed order; at N = 60,000 it holds the
+device's own choice and the results are bitwise equal.  The oracle pins the
+second call too.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_20787_amd as m
+    return m
+
+
+def rel(a, ref):
+    a = a.double().cpu().numpy()
+    r = ref.double().cpu().numpy() if hasattr(ref, "cpu") else ref
+    return np.linalg.norm(a - r, axis=0) / np.linalg.norm(r, axis=0)
+
+
+def test_noalloc_matches_the_allocating_entry_point_on_two_calls(sc):
+    d = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(d)
+    for N, seed in ((300000, 1), (60000, 2)):
+        p = synth.cylinder_load(N, seed=seed)
+        pos, m, e = (torch.from_numpy(x).to(d) for x in (p.pos, p.mass, p.eps))
+        acc = torch.full((3, N), np.nan, dtype=torch.float32, device=d)
+        pot = torch.full((N,), np.nan, dtype=torch.float32, device=d)
+        print(f"[case] noalloc N={N}", flush=True)
+        rc = sc.lib().steps_cyl_forces_noalloc(pos.data_ptr(), m.data_ptr(), e.data_ptr(), N, p.L, 8,
+                                               acc.data_ptr(), pot.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+        assert rc == sc.STEPS_OK, sc.steps_cyl_last_error()
+        ref_acc, ref_pot = sc.steps_cyl_forces(pos, m, e, p.L, 8)
+        torch.cuda.synchronize()
+        assert torch.isfinite(acc).all() and torch.isfinite(pot).all()
+        assert rel(acc, ref_acc).max() <= 1e-5
+        assert (torch.abs(pot.double() - ref_pot.double()) / torch.abs(ref_pot.double())).max().item() <= 1e-5
+        same = torch.equal(acc, ref_acc) and torch.equal(pot, ref_pot)
+        print(f"N={N}: bitwise equal to steps_cyl_forces: {same}")
+        if N <= 60000:
+            assert same
+    # the second (smaller) call against the oracle on a sample of targets
+    t = synth.target_sample(N, 200, seed=3)
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 8, targets=t)
+    assert rel(acc[:, torch.from_numpy(t).to(d)], a_ref).max() <= 1e-5
