@@ -10,10 +10,10 @@ with HIP events on the stream the kernels run on.
 Secondary legs (each timed as the median of several runs after a warm-up):
   * one_sided: the per-target kernel over all targets;
   * precision_c3: FP32 pair terms with Kahan per-target sums, with plain FP32
-    sums and the pairwise FP64-sum path against the FP64 GPU reference on
-    8192 targets of the same load (max, rms and 99.9th-percentile relative
-    acceleration error, potential error), the reference itself against the
-    CPU oracle on 256 of them;
+    sums (both over all N sources per target) and the pairwise FP64-sum path
+    against the FP64 GPU reference on 8192 targets of the same load (max, rms
+    and 99.9th-percentile relative acceleration error, potential error), the
+    reference itself against the CPU oracle on 256 of them;
   * learned: at --learned-n particles (default 2^20), the learned far-image
     correction (every unordered pair once), the 144 x 128 correction tables
     (CIC, TSC) and the exact |n| <= 1024 sum (per-target kernel on a subset of
@@ -52,8 +52,8 @@ PEAK_FP32_UNPACKED = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 # what the counter reads for a 256 MiB copy
 # (profiles/forces_pairwise_N1M_nimg8_counters.md).  Valid only for the
 # kernel sources they were measured on (hash below); None until measured.
-TRAFFIC_EXACT_N1M = {"bytes": None, "fetch_scale": 1.99969, "write_scale": 1.0,
-                     "sources_sha256_16": None}
+TRAFFIC_EXACT_N1M = {"bytes": 3.1667e11, "fetch_scale": 1.99974, "write_scale": 1.0,
+                     "sources_sha256_16": "172db70680025d97"}
 TRAFFIC_SOURCES = ["forces_pairwise.hip", "pair_fp32.h", "pair_f64.h", "target_order.hip"]
 
 
@@ -73,21 +73,28 @@ def flops_per_pair(n_img, potential=True):
 # the reaction on the source: m_i S (1) and three FMAs for a (6) plus one for
 # the potential (2)
 REACTION_FLOPS = 9
-PAIRWISE_GROUP = 1024
+
+
+def pairwise_group(N):
+    """Particles per group of the exact pairwise path: 16 parts of 256 up to
+    2^21 particles, else 8."""
+    return 256 * (16 if N <= (1 << 21) else 8)
 
 
 def pairwise_evaluations(N):
     """Pair terms the pairwise kernels evaluate: every ordered pair inside a
-    group of PAIRWISE_GROUP particles, every pair across groups once."""
-    full, tail = divmod(N, PAIRWISE_GROUP)
-    inner = full * PAIRWISE_GROUP ** 2 + tail ** 2
+    group, every pair across groups once."""
+    g = pairwise_group(N)
+    full, tail = divmod(N, g)
+    inner = full * g ** 2 + tail ** 2
     return (N * N + inner) // 2
 
 
 def meeting_launches(N):
     """Launches of the meeting kernel per call: G' - 1 tournament rounds,
     G' the group count rounded up to even."""
-    G = (N + PAIRWISE_GROUP - 1) // PAIRWISE_GROUP
+    g = pairwise_group(N)
+    G = (N + g - 1) // g
     return G + (G & 1) - 1
 
 
@@ -156,7 +163,7 @@ def exact_leg(args, dev):
     ms = float(np.mean(step_ms))
     pairs = float(N) * float(N)
     value = pairs / (ms * 1e-3) / 1e9
-    # the kernels evaluate each unordered pair once (groups of PAIRWISE_GROUP
+    # the kernels evaluate each unordered pair once (groups of pairwise_group(N)
     # particles: all ordered pairs inside a group, each cross pair once) and
     # apply it to both particles; the whole call (ordering, staging, the self
     # launch, the tournament's launches and the final pass) is the time base
@@ -207,8 +214,8 @@ def exact_leg(args, dev):
             "time_base": "whole steps_cyl_forces call",
             "meeting_launches_per_call": meeting_launches(N),
             "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_UNPACKED, 4),
-            "kernel": f"forces_pairwise_kernel<{n_img},true,0,false,true> (tournament meetings; "
-                      f"plus one self launch <{n_img},true,0,false,false>)",
+            "kernel": f"forces_pairwise_kernel<{n_img},true,0,false,true> (tournament meetings, one-wave "
+                      f"workgroups; plus one self launch <{n_img},true,0,false,false>)",
         },
         # the metric's N^2 count (F_pair for every ordered pair, including the
         # half that symmetry skips): a dense-equivalent figure
@@ -248,16 +255,18 @@ def exact_leg(args, dev):
         out["max_rel_pot_err"] = st["pot_max"]
         out["err_sample_targets"] = k
     if args.precision_targets:
-        out["precision_c3"] = precision_leg(args, dev, p, pos, m, e, acc, pot)
+        out["precision_c3"] = precision_leg(args, dev, p, pos, m, e, acc, pot, acc1, pot1)
     return out
 
 
-def precision_leg(args, dev, p, pos, m, e, acc, pot):
+def precision_leg(args, dev, p, pos, m, e, acc, pot, acc_comp, pot_comp):
     """C3's precision study on the exact leg's load: FP32 pair terms with
-    Kahan-compensated per-target sums, with plain FP32 per-target sums, and
-    the pairwise path (FP64 sums; the exact leg's result), each against the
-    FP64 GPU reference on the same targets; the reference against the CPU
-    oracle on a subset."""
+    Kahan-compensated per-target sums (the one-sided leg's all-target call),
+    with plain FP32 per-target sums over all N sources (an all-target call, so
+    that no target's sum is split into source chunks), and the pairwise path
+    (FP64 sums; the exact leg's result), each against the FP64 GPU reference
+    on the same sampled targets; the reference against the CPU oracle on a
+    subset."""
     import numpy as np
     import torch
 
@@ -269,8 +278,7 @@ def precision_leg(args, dev, p, pos, m, e, acc, pot):
     t = torch.from_numpy(tg).to(dev)
     print(f"[bench] precision study on {k} targets", file=sys.stderr, flush=True)
     ref, ref_pot = sc.steps_cyl_forces_f64(pos, m, e, p.L, n_img, targets=t)
-    comp, comp_pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, n_img, targets=t, mode=sc.STEPS_SUM_COMPENSATED)
-    plain, plain_pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, n_img, targets=t, mode=sc.STEPS_SUM_PLAIN)
+    plain, plain_pot = sc.steps_cyl_forces_ex(pos, m, e, p.L, n_img, mode=sc.STEPS_SUM_PLAIN)
     torch.cuda.synchronize()
     r, rp = ref.cpu().numpy(), ref_pot.cpu().numpy()
 
@@ -279,8 +287,8 @@ def precision_leg(args, dev, p, pos, m, e, acc, pot):
     out = {
         "N": N, "n_img": n_img, "targets": k,
         "reference": "FP64 GPU direct sum (steps_cyl_forces_f64) on the same targets",
-        "compensated_fp32": err_stats(host(comp), r, host(comp_pot), rp),
-        "plain_fp32": err_stats(host(plain), r, host(plain_pot), rp),
+        "compensated_fp32": err_stats(host(acc_comp)[:, tg], r, host(pot_comp)[tg], rp),
+        "plain_fp32": err_stats(host(plain)[:, tg], r, host(plain_pot)[tg], rp),
         "pairwise_fp64_sums": err_stats(host(acc)[:, tg], r, host(pot)[tg], rp),
     }
     if not args.no_cpu_baseline:

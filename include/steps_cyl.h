@@ -123,13 +123,12 @@ typedef struct steps_cyl_table steps_cyl_table;   /* opaque; owns device memory 
  * Arithmetic: pair separations and the z wrap in FP64, FP32 pair terms,
  * FP64 sums.  Groups of 1024 particles in spatial order meet in a fixed
  * round-robin tournament (one launch per round, no atomics), so repeated
- * calls on one device are bitwise equal.  Total momentum is conserved to the
- * rounding of the sums.  Workspace (stream-ordered here; see
- * steps_cyl_forces_ws): 32 bytes per particle for the records, 32 P bytes
- * per particle for the sums (P in 1..16 workgroups per meeting, chosen to
- * fill the device: 1 at N = 2^20) and 1 byte per particle for boxes, plus
- * the spatial order's 16 bytes per particle and radix-sort storage.  Returns
- * STEPS_OK, or STEPS_EINVAL / STEPS_ENOMEM / STEPS_EHIP.
+ * calls are bitwise equal.  Total momentum is conserved to the rounding of
+ * the sums.  Workspace (stream-ordered here; see steps_cyl_forces_ws): 32
+ * bytes per particle for the records, 64 S for 2S slots of FP64 sums (S = 16
+ * parts per group up to N = 2^21, else 8), 1 for boxes, plus the spatial
+ * order's 16 bytes per particle and radix-sort storage (about 1.05 GiB at
+ * N = 2^20).  Returns STEPS_OK, or STEPS_EINVAL / STEPS_ENOMEM / STEPS_EHIP.
  */
 int steps_cyl_forces(const double *pos, const double *mass, const double *eps,
                      int64_t N, double L, int n_img,
@@ -168,17 +167,17 @@ int steps_cyl_forces_ws(const double *pos, const double *mass, const double *eps
  * steps_cyl_forces_noalloc -- steps_cyl_forces for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the same pairwise path and arguments,
- * with its workspace in a fixed 96 MiB array of the library's device image
+ * with its workspace in a fixed 128 MiB array of the library's device image
  * instead of per-call memory.  Each device the library runs on holds its own
  * copy of the array until the process ends.  Calls no allocator.
  *
  *   N   1 <= N <= STEPS_NOALLOC_MAX_N (2^20); larger N return STEPS_EINVAL
  *       with a message naming the limit, before any device work
  *
- * The workgroups per meeting are the device's choice or fewer, so that the
- * workspace fits the array; where they are fewer the sums run in another
- * (fixed) order than in steps_cyl_forces and the results agree with it to
- * FP32 rounding, otherwise bit for bit.  Every call on a device shares that
+ * Groups hold 16 parts as in steps_cyl_forces, or fewer (fewer sum slots)
+ * where the workspace would not fit the array (above N = 125,000); with
+ * fewer the sums run in another (fixed) order than in steps_cyl_forces and
+ * the results agree with it to FP32 rounding, otherwise bit for bit.  Every call on a device shares that
  * device's array and finds it as the last call left it (nothing in it needs
  * to start at zero): calls that overlap on one device, on different streams
  * or from different threads, race and give undefined results.

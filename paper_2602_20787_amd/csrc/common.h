@@ -80,16 +80,15 @@ int check_workspace(const Workspace &ws, size_t need);
 // The pairwise path (forces_pairwise.hip) for all N particles: every
 // unordered pair once, exact images |n| <= n_img, or with a table (non-null)
 // images |n| <= 1 plus its far images (order 1 CIC, 2 TSC).  Arguments are
-// validated by the caller; pairwise_bytes() is the workspace it takes on
-// the current device (0 if the device cannot be queried).
-// p_cap > 0 caps the workgroups per meeting (P, a power of two) below the
-// device's choice; pairwise_bytes_P() is the workspace with P workgroups
-// per meeting.
+// validated by the caller; pairwise_bytes() is the workspace it takes.
+// s_cap > 0 caps the parts per group (S, a power of two up to 16), which
+// sets the sum slots (2S per particle); pairwise_bytes_S() is the workspace
+// with S parts per group.
 size_t pairwise_bytes(int64_t N, int n_img, const steps_cyl_table *table, int order, bool pot);
-size_t pairwise_bytes_P(int64_t N, int P);
+size_t pairwise_bytes_S(int64_t N, int S);
 int launch_forces_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
                            int n_img, const steps_cyl_table *table, int order, float *out_acc, float *out_pot,
-                           Workspace &ws, hipStream_t stream, int p_cap = 0);
+                           Workspace &ws, hipStream_t stream, int s_cap = 0);
 
 // The learned correction's pairwise path for all N particles
 // (forces_learned.hip); arguments validated by the caller.

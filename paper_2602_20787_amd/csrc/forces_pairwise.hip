@@ -11,9 +11,11 @@
 // (forces_exact.hip, table.hip).
 //
 // Layout.  The particles are put in spatial (Morton) order and staged as
-// 32-byte records {x, y, z wrapped, m, h}; groups of 1024 consecutive
-// records (512 with a table) are the unit of work.  Each particle has P
-// slots of FP64 sums (x, y, z, potential).
+// 32-byte records {x, y, z wrapped, m, h}, with a bounding box per run of 64
+// records.  A part is 64 kR consecutive records (kR = 4 particles per lane,
+// 2 with a table); a group is S parts (S = 16 up to 2^21 particles, else 8;
+// 8 with a table).  Each particle has 2S slots of FP64 sums (x, y, z,
+// potential).
 //
 // Schedule (bitwise deterministic, no atomics).  A first launch pairs every
 // group with itself (one-sided, every ordered pair, the self pair skipped)
@@ -21,25 +23,26 @@
 // even) follow a round-robin tournament: in round r group G'-1 meets group
 // r and, for k = 1 .. G'/2 - 1, group (r + k) mod (G'-1) meets group
 // (r - k) mod (G'-1), so every unordered pair of groups meets exactly once
-// and no group appears twice in a round.  P workgroups share a meeting:
-// workgroup q holds group a's particles in registers and streams chunk q of
-// group b.  Within a launch the sums a workgroup touches are its own: slot q
-// of group a (a's sums from chunk q) and slot 0 of chunk q of group b (the
-// reactions), so every sum is a plain read-modify-write in an order fixed by
-// (N, P).  A last pass adds the slots in order and writes FP32 outputs at the
-// particles' own positions.
+// and no group appears twice in a round.  A meeting of groups a and b takes
+// S^2 workgroups of one wave: workgroup (i, j) holds part i of a in
+// registers and streams part j of b, adding a's sums into slot j of part i
+// and b's reactions into slot S + i of part j.  Within a launch each slot
+// has one writer, so every sum is a plain read-modify-write in an order
+// fixed by (N, S).  A last pass adds the slots in order and writes FP32
+// outputs at the particles' own positions.
 //
-// Workgroup.  256 threads own the particles of group a, 4 each (2 with a
-// table), in registers; a wave's particles are 256 (128) consecutive
-// records.  Sources come through LDS in tiles of 256, as 64-source
-// sub-tiles: at step s lane l takes source (l + s) mod 64 of the sub-tile,
-// so that within a wave no two lanes meet the same source at once.  The
-// reaction on a source is summed in FP64 in an LDS slot that the wave's lanes
-// update in turn (64 steps visit every lane); after the tile the 4 waves'
-// slots are added in order.  A sub-tile whose bounding box is far from the
-// wave's (no pair closer than the sum of the largest softenings, no axial
-// separation near L/2) skips the softening and half-period screens; the pair
-// arithmetic is the same either way.
+// Workgroup.  One wave owns its part, kR particles per lane, in registers;
+// the part's sources come through LDS as kR sub-tiles of 64: at step s lane
+// l takes source (l + s) mod 64 of the sub-tile, so no two lanes meet the
+// same source at once.  The reaction on a source is summed in FP64 in an
+// LDS slot that the lanes update in turn (64 steps visit every lane).  A
+// sub-tile whose bounding box is far from the wave's (no pair closer than
+// the sum of the largest softenings, no axial separation near L/2) skips the
+// softening and half-period screens and the per-pair minimum image; the pair
+// arithmetic is the same either way.  One-wave workgroups need no barrier
+// between waves, and a workgroup's memory traffic (its part's records and
+// both parts' sums) is shared by 4096 (1024) pairs per particle pair of
+// parts, twice what a 1024-particle workgroup streaming 64 sources moves.
 #include <algorithm>
 
 #include "common.h"
@@ -51,20 +54,19 @@ namespace steps {
 
 namespace {
 
-constexpr int kThreads = 256;  // 4 waves
-constexpr int kWaves = kThreads / 64;
-// particles per thread: 4 for the exact pair (the reaction's LDS update is
+constexpr int kThreads = 64;  // one wave
+// particles per lane: 4 for the exact pair (the reaction's LDS update is
 // shared by more pairs); 2 with a table, whose gathers want the occupancy
 // that the smaller register set gives
 constexpr int particles_per_thread(int torder) { return torder > 0 ? 2 : 4; }
-constexpr int kTile = 256;  // sources per LDS tile
-constexpr int kSub = 64;    // sources per sub-tile (one wave's rotation)
+constexpr int kMaxR = 4;
+constexpr int kSub = 64;    // sources per sub-tile (one rotation)
 constexpr int kBox = 8;     // doubles per 64-record box
 
 struct PairwiseArgs {
     const SrcRec *rec;   // [N] records in spatial order
     const double *box;   // [ceil(N/64)][8] bounding boxes of aligned runs of 64 records
-    double *sum;         // [P][4][N] FP64 sums in spatial order (x, y, z, potential)
+    double *sum;         // [2S][4][N] FP64 sums in spatial order (x, y, z, potential)
     double L, invL, halfL, tie;  // tie: |d| within this of L/2 takes the check
     double far_h;                // largest softening sum for which the fast path is allowed
     float tie32;                 // FP32 screen for it: 0.5 L (1 - 1e-6), below every such |d|
@@ -72,7 +74,7 @@ struct PairwiseArgs {
     TableView tv;  // far-image table (table paths only)
     float invLf, invL2f;
     int N, G, Gp;  // particles, groups, groups rounded up to even
-    int P, chunk;  // workgroups per meeting, sources per workgroup (multiple of 64)
+    int S;         // parts per group (1, 2, 4, 8 or 16)
     int round;     // tournament round (launches of the meetings)
 };
 
@@ -147,12 +149,12 @@ __global__ void box_kernel(const SrcRec *rec, int N, double *box) {
     }
 }
 
-__global__ void finish_kernel(const double *sum, int P, const int *perm, int N, float *ax, float *ay, float *az,
+__global__ void finish_kernel(const double *sum, int slots, const int *perm, int N, float *ax, float *ay, float *az,
                               float *pot) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int q = 0; q < P; ++q)
+    for (int q = 0; q < slots; ++q)
         for (int c = 0; c < 4; ++c) s[c] += sum[((int64_t)q * 4 + c) * N + k];
     const int p = perm[k];
     // attraction: a = -sum m_j S (x_i - x_j), potential = -sum m_j / r
@@ -201,12 +203,12 @@ __device__ __forceinline__ bool far_boxes(const PairwiseArgs &a, const WaveBox &
     return gx * gx + gy * gy + gz * gz > hs * hs * (1.0 + 1e-4) + 1e-300;
 }
 
-// LDS of a workgroup: the tile's sources (SoA) and the waves' FP64 reaction
-// slots.
+// LDS of a workgroup: its part's sources (SoA) and their FP64 reaction slots.
+template <int kR>
 struct Stage {
-    double x[kTile], y[kTile], z[kTile];
-    float m[kTile], h[kTile];
-    double r[kWaves][4][kTile];  // reactions, FP64
+    double x[64 * kR], y[64 * kR], z[64 * kR];
+    float m[64 * kR], h[64 * kR];
+    double r[4][64 * kR];  // reactions, FP64
 };
 
 // Reaction on the source from an evaluated pair, in the owned sums'
@@ -272,9 +274,9 @@ __device__ __forceinline__ void table_far(const PairwiseArgs &a, float dx, float
 // near_pass, with no per-pair floor).  No softening, no half-period screen.
 // FP32 pair terms, FP64 sums and reactions as in near_pass.
 template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT, int kR>
-__device__ __forceinline__ void far_pass(const PairwiseArgs &a, const Owned<kR> &o, Stage &st, int s, double kL,
+__device__ __forceinline__ void far_pass(const PairwiseArgs &a, const Owned<kR> &o, Stage<kR> &st, int s, double kL,
                                          double (*acc)[4]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     double zs[kR];
 #pragma unroll
     for (int r = 0; r < kR; ++r) zs[r] = o.z[r] - kL;
@@ -285,10 +287,10 @@ __device__ __forceinline__ void far_pass(const PairwiseArgs &a, const Owned<kR> 
         double jx = 0.0, jy = 0.0, jz = 0.0, jp = 0.0;
         if (REACT && step > 0) {
             // the slot as the previous lane left it
-            jx = st.r[wave][0][k];
-            jy = st.r[wave][1][k];
-            jz = st.r[wave][2][k];
-            if (POT) jp = st.r[wave][3][k];
+            jx = st.r[0][k];
+            jy = st.r[1][k];
+            jz = st.r[2][k];
+            if (POT) jp = st.r[3][k];
         }
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
@@ -312,10 +314,10 @@ __device__ __forceinline__ void far_pass(const PairwiseArgs &a, const Owned<kR> 
             }
         }
         if (REACT) {
-            st.r[wave][0][k] = jx;
-            st.r[wave][1][k] = jy;
-            st.r[wave][2][k] = jz;
-            if (POT) st.r[wave][3][k] = jp;
+            st.r[0][k] = jx;
+            st.r[1][k] = jy;
+            st.r[2][k] = jz;
+            if (POT) st.r[3][k] = jp;
         }
     }
 }
@@ -329,12 +331,12 @@ __device__ __forceinline__ void far_pass(const PairwiseArgs &a, const Owned<kR> 
 // images n != 0 may be softened too and the pair is evaluated in FP64 with
 // the spline on every image (rare: one pair per lane and pass).  REACT: the
 // sources belong to another group and their reactions are summed in the
-// wave's FP64 LDS slots; otherwise (the group against itself) the self pair
-// is skipped.
+// FP64 LDS slots; otherwise (the group against itself) the self pair is
+// skipped.
 template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT, int kR>
-__device__ __forceinline__ void near_pass(const PairwiseArgs &a, const Owned<kR> &o, Stage &st, int s, int base,
+__device__ __forceinline__ void near_pass(const PairwiseArgs &a, const Owned<kR> &o, Stage<kR> &st, int s, int base,
                                           float hmax, double (*acc)[4]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     float thr2[kR];
     bool wide[kR];
 #pragma unroll
@@ -430,10 +432,10 @@ __device__ __forceinline__ void near_pass(const PairwiseArgs &a, const Owned<kR>
         double jx = 0.0, jy = 0.0, jz = 0.0, jp = 0.0;
         if (REACT && step > 0) {
             // the slot as the previous lane left it
-            jx = st.r[wave][0][k];
-            jy = st.r[wave][1][k];
-            jz = st.r[wave][2][k];
-            if (POT) jp = st.r[wave][3][k];
+            jx = st.r[0][k];
+            jy = st.r[1][k];
+            jz = st.r[2][k];
+            if (POT) jp = st.r[3][k];
         }
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
@@ -453,23 +455,26 @@ __device__ __forceinline__ void near_pass(const PairwiseArgs &a, const Owned<kR>
             }
         }
         if (REACT) {
-            st.r[wave][0][k] = jx;
-            st.r[wave][1][k] = jy;
-            st.r[wave][2][k] = jz;
-            if (POT) st.r[wave][3][k] = jp;
+            st.r[0][k] = jx;
+            st.r[1][k] = jy;
+            st.r[2][k] = jz;
+            if (POT) st.r[3][k] = jp;
         }
     }
 }
 
-// One meeting (REACT: group a against chunk q of group b in tournament round
-// a.round) or one self meeting (group a against chunk q of itself).
+// Workgroup (i, j) of one meeting (REACT: the groups of tournament round
+// a.round) or of one group's meeting with itself: part i of group a against
+// part j of group b.
 template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT>
 __global__ __launch_bounds__(kThreads, TORDER > 0 ? 3 : 2) void forces_pairwise_kernel(PairwiseArgs a) {
     constexpr int kR = particles_per_thread(TORDER);
-    constexpr int kGroup = kThreads * kR;  // particles per group
-    __shared__ Stage st;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int meet = blockIdx.x / a.P, q = blockIdx.x % a.P;
+    constexpr int kPart = 64 * kR;  // particles per part
+    __shared__ Stage<kR> st;
+    const int lane = threadIdx.x;
+    const int S = a.S;
+    const int meet = blockIdx.x / (S * S);
+    const int pi = (blockIdx.x / S) % S, pj = blockIdx.x % S;
     int ga = meet, gb = meet;
     if (REACT) {
         const int M = a.Gp - 1;
@@ -480,17 +485,21 @@ __global__ __launch_bounds__(kThreads, TORDER > 0 ? 3 : 2) void forces_pairwise_
             ga = (a.round + meet) % M;
             gb = (a.round - meet + M) % M;
         }
-        if (ga >= a.G || gb >= a.G) return;  // the empty group of an odd count (whole workgroup)
+        if (ga >= a.G || gb >= a.G) return;  // the empty group of an odd count
     }
+    const int64_t g0 = ((int64_t)ga * S + pi) * kPart;  // first owned record
+    if (g0 >= a.N) return;                              // an empty part: nothing owned
+    const int64_t b0 = ((int64_t)gb * S + pj) * kPart;  // first source record
+    const int cnt = (int)max((int64_t)0, min((int64_t)kPart, (int64_t)a.N - b0));
+    if (REACT && cnt == 0) return;                      // no sources: nothing to add
 
-    // the wave's particles: records ga*kGroup + wave*64*kR + r*64 + lane;
-    // empty slots copy the group's first record with no mass (they sit where
-    // a particle is, so every pair distance stays that of a real pair)
+    // the owned particles: records g0 + r*64 + lane; empty slots copy the
+    // part's first record with no mass (they sit where a particle is, so
+    // every pair distance stays that of a real pair)
     Owned<kR> o;
-    const int64_t g0 = (int64_t)ga * kGroup;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-        const int64_t t64 = g0 + (int64_t)wave * 64 * kR + r * 64 + lane;
+        const int64_t t64 = g0 + r * 64 + lane;
         const bool real = t64 < a.N;
         const SrcRec rr = a.rec[real ? t64 : g0];
         o.t[r] = real ? (int)t64 : a.N;
@@ -500,7 +509,7 @@ __global__ __launch_bounds__(kThreads, TORDER > 0 ? 3 : 2) void forces_pairwise_
         o.h[r] = rr.h;
         o.m[r] = real ? rr.m : 0.f;
     }
-    // the wave's bounding box (every lane ends with it)
+    // the part's bounding box (every lane ends with it)
     WaveBox wb;
     {
         double v[7] = {o.x[0], -o.x[0], o.y[0], -o.y[0], o.z[0], -o.z[0], (double)o.h[0]};
@@ -532,62 +541,65 @@ __global__ __launch_bounds__(kThreads, TORDER > 0 ? 3 : 2) void forces_pairwise_
     for (int r = 0; r < kR; ++r)
         for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
 
-    const int64_t cb64 = (int64_t)gb * kGroup + (int64_t)q * a.chunk;
-    const int cbeg = (int)min(cb64, (int64_t)a.N), cend = (int)min(cb64 + a.chunk, (int64_t)a.N);
-    for (int base = cbeg; base < cend; base += kTile) {
-        const int cnt = min(kTile, cend - base);
-        const int nsub = (cnt + kSub - 1) / kSub;
-        // stage the tile; a partly filled sub-tile is padded with massless
-        // copies of its first record (inside its box)
-        if (tid < nsub * kSub) {
-            const int first = base + (tid & ~(kSub - 1));
-            const bool real = tid < cnt;
-            const SrcRec rr = a.rec[real ? base + tid : first];
-            st.x[tid] = rr.x;
-            st.y[tid] = rr.y;
-            st.z[tid] = rr.z;
-            st.m[tid] = real ? rr.m : 0.f;
-            st.h[tid] = rr.h;
-        }
-        __syncthreads();
-        for (int s = 0; s < nsub; ++s) {
-            const double *b = a.box + (int64_t)((base >> 6) + s) * kBox;
-            double kL = 0.0;
-            const bool far = far_boxes(a, wb, b, kL);
-            if (__builtin_amdgcn_readfirstlane((int)far))
-                far_pass<NIMG, POT, TORDER, COMPLETE, REACT>(a, o, st, s, kL, acc);
-            else
-                near_pass<NIMG, POT, TORDER, COMPLETE, REACT>(a, o, st, s, base, (float)b[6], acc);
-        }
-        __syncthreads();
-        if (REACT && tid < cnt) {
-            // reaction on source base + tid, in the owned sums' orientation:
-            // the 4 waves' slots in order, added to slot 0 of the source
-            const int64_t jj = base + tid;
+    // stage the sources; a partly filled sub-tile is padded with massless
+    // copies of its first record (inside its box)
+    const int nsub = (cnt + kSub - 1) / kSub;
+    const int base = (int)b0;  // b0 < N <= 2^29 whenever cnt > 0
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (c == 3 && !POT) continue;
-                const double v = (st.r[0][c][tid] + st.r[1][c][tid]) + (st.r[2][c][tid] + st.r[3][c][tid]);
-                double *p = a.sum + (int64_t)c * a.N + jj;
-                *p = (c == 3) ? *p + v : *p - v;
+    for (int r = 0; r < kR; ++r) {
+        const int t = r * 64 + lane;
+        if (t < nsub * kSub) {
+            const bool real = t < cnt;
+            const SrcRec rr = a.rec[real ? base + t : base + (t & ~(kSub - 1))];
+            st.x[t] = rr.x;
+            st.y[t] = rr.y;
+            st.z[t] = rr.z;
+            st.m[t] = real ? rr.m : 0.f;
+            st.h[t] = rr.h;
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < nsub; ++s) {
+        const double *b = a.box + (int64_t)((base >> 6) + s) * kBox;  // base is a multiple of 64
+        double kL = 0.0;
+        const bool far = far_boxes(a, wb, b, kL);
+        if (__builtin_amdgcn_readfirstlane((int)far))
+            far_pass<NIMG, POT, TORDER, COMPLETE, REACT>(a, o, st, s, kL, acc);
+        else
+            near_pass<NIMG, POT, TORDER, COMPLETE, REACT>(a, o, st, s, base, (float)b[6], acc);
+    }
+    __syncthreads();
+    if (REACT) {
+        // reactions on the sources, in the owned sums' orientation, into
+        // slot S + pi of part pj
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int t = r * 64 + lane;
+            if (t < cnt) {
+                double *p = a.sum + ((int64_t)(S + pi) * 4) * a.N + base + t;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (c == 3 && !POT) continue;
+                    const double v = st.r[c][t];
+                    p[(int64_t)c * a.N] = (c == 3) ? p[(int64_t)c * a.N] + v : p[(int64_t)c * a.N] - v;
+                }
             }
         }
-        // the next tile's staging overwrites only the source arrays, which
-        // every wave has finished reading at the barrier above; the slots are
-        // written again only after the next barrier
     }
-    // the group's own sums from this chunk: slot q
+    // the owned particles' sums from part pj: slot pj; the self meeting
+    // initialises it and clears the reaction slot S + pj
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         if (o.t[r] < a.N) {
-            double *p = a.sum + (int64_t)q * 4 * a.N + o.t[r];
+            double *p = a.sum + (int64_t)pj * 4 * a.N + o.t[r];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                if (c == 3 && !POT) continue;
-                if (REACT)
-                    p[(int64_t)c * a.N] += acc[r][c];
-                else
-                    p[(int64_t)c * a.N] = acc[r][c];  // the self meeting initialises every slot
+                if (REACT) {
+                    if (c < 3 || POT) p[(int64_t)c * a.N] += acc[r][c];
+                } else {
+                    p[(int64_t)c * a.N] = acc[r][c];
+                    p[((int64_t)S * 4 + c) * a.N] = 0.0;
+                }
             }
         }
     }
@@ -595,22 +607,15 @@ __global__ __launch_bounds__(kThreads, TORDER > 0 ? 3 : 2) void forces_pairwise_
 
 template <int NIMG, bool POT, int TORDER, bool COMPLETE>
 struct Launcher {
-    // workgroups of the meeting kernel resident per CU
-    static int blocks_per_cu() {
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE, true>,
-                                                         kThreads, 0) != hipSuccess)
-            n = 1;
-        return std::max(1, n);
-    }
     static hipError_t run(PairwiseArgs a, hipStream_t stream) {
-        hipLaunchKernelGGL((forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE, false>), dim3(a.G * a.P),
+        const unsigned per_meeting = (unsigned)(a.S * a.S);
+        hipLaunchKernelGGL((forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE, false>), dim3(a.G * per_meeting),
                            dim3(kThreads), 0, stream, a);
         hipError_t e = hipGetLastError();
         for (int r = 0; e == hipSuccess && r + 1 < a.Gp; ++r) {
             a.round = r;
-            hipLaunchKernelGGL((forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE, true>), dim3(a.Gp / 2 * a.P),
-                               dim3(kThreads), 0, stream, a);
+            hipLaunchKernelGGL((forces_pairwise_kernel<NIMG, POT, TORDER, COMPLETE, true>),
+                               dim3(a.Gp / 2 * per_meeting), dim3(kThreads), 0, stream, a);
             e = hipGetLastError();
         }
         return e;
@@ -648,50 +653,28 @@ auto dispatch(int n_img, bool pot, int order, bool complete, F &&f) {
     return complete ? f(Launcher<1, false, 2, true>{}) : f(Launcher<1, false, 2, false>{});
 }
 
-// Workgroups per meeting: the smallest P (chunks of kGroup/P sources, at
-// least one 64-source sub-tile) whose launches hold at least 16 times the
-// workgroups the device keeps resident, else the largest.  A launch ends
-// with its slowest workgroup (a near meeting, with many pairs on the
-// general path), so short workgroups in many waves keep that tail small;
-// each step of P adds one slot of FP64 sums per particle.  `resident` is the
-// number of workgroups the device holds at once for the meeting kernel.
-int choose_P(int Gp, int kGroup, int resident) {
-    const int64_t meetings = Gp / 2;
-    int P = 1;
-    while (P < kGroup / kSub && meetings * P < (int64_t)16 * resident) P *= 2;
-    return P;
-}
-
-// Workgroups per meeting (P) and particles per group of a pairwise call on
-// the current device.
-int pairwise_plan(int64_t N, const steps_cyl_table *table, int order, int n_img, bool pot, int *P, int *group) {
-    const int kR = particles_per_thread(table ? 1 : 0);
-    *group = kThreads * kR;
-    const int G = (int)((N + *group - 1) / *group);
-    const int Gp = G + (G & 1);
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_status(e, "device attributes");
-    const int ord = table ? order : 0;
-    const bool complete = table && table->complete != 0;
-    const int per_cu = dispatch(table ? 1 : n_img, pot, ord, complete, [](auto l) { return l.blocks_per_cu(); });
-    *P = choose_P(Gp, *group, per_cu * std::max(1, cus));
-    return STEPS_OK;
-}
-
 }  // namespace
 
-size_t pairwise_bytes_P(int64_t N, int P) {
-    const int64_t nbox = (N + 63) / 64;
-    return ws_total({order_targets_bytes(N), (size_t)N * sizeof(SrcRec), (size_t)nbox * kBox * sizeof(double),
-                     (size_t)P * 4 * N * sizeof(double)});
+// Parts per group of a pairwise call.  More parts make a launch hold more,
+// shorter workgroups (its tail is one of them) at the price of 2 sum slots
+// (64 B) per particle each.  Measured per call at N = 2^20: S = 4, 8, 16 took
+// 2341, 2231 and 2181 ms (exact), and S = 8, 16 CIC 1465 and 1503 ms (the
+// table kernel's parts are half as large); at N = 2^21 S = 8, 16 took 8681
+// and 8559 ms.  Above 2^21 particles a call has enough meetings with S = 8
+// and the slots would grow past 2 GiB.
+int pairwise_parts(int64_t N, const steps_cyl_table *table) {
+    if (table) return 8;
+    return N <= ((int64_t)1 << 21) ? 16 : 8;
 }
 
-size_t pairwise_bytes(int64_t N, int n_img, const steps_cyl_table *table, int order, bool pot) {
-    int P = 1, group = 0;
-    if (pairwise_plan(N, table, order, n_img, pot, &P, &group) != STEPS_OK) return 0;
-    return pairwise_bytes_P(N, P);
+size_t pairwise_bytes_S(int64_t N, int S) {
+    const int64_t nbox = (N + 63) / 64;
+    return ws_total({order_targets_bytes(N), (size_t)N * sizeof(SrcRec), (size_t)nbox * kBox * sizeof(double),
+                     (size_t)2 * S * 4 * N * sizeof(double)});
+}
+
+size_t pairwise_bytes(int64_t N, int, const steps_cyl_table *table, int, bool) {
+    return pairwise_bytes_S(N, pairwise_parts(N, table));
 }
 
 // Launches the pairwise path for all N particles: exact images |n| <= n_img,
@@ -700,12 +683,12 @@ size_t pairwise_bytes(int64_t N, int n_img, const steps_cyl_table *table, int or
 // Scratch (spatial order, records, boxes, FP64 sums) comes from `ws`.
 int launch_forces_pairwise(const double *pos, const double *mass, const double *eps, int64_t N, double L,
                            int n_img, const steps_cyl_table *table, int order, float *out_acc, float *out_pot,
-                           Workspace &ws, hipStream_t stream, int p_cap) {
-    int P = 1, group = 0;
-    int rc = pairwise_plan(N, table, order, n_img, out_pot != nullptr, &P, &group);
+                           Workspace &ws, hipStream_t stream, int s_cap) {
+    int S = pairwise_parts(N, table);
+    if (s_cap > 0) S = std::min(S, s_cap);
+    int rc = check_workspace(ws, pairwise_bytes_S(N, S));
     if (rc) return rc;
-    if (p_cap > 0) P = std::min(P, p_cap);
-    if ((rc = check_workspace(ws, pairwise_bytes_P(N, P)))) return rc;
+    const int group = 64 * particles_per_thread(table ? 1 : 0) * S;
     PairwiseArgs a;
     a.L = L;
     a.invL = 1.0 / L;
@@ -724,8 +707,7 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
     a.G = (int)((N + group - 1) / group);
     a.Gp = a.G + (a.G & 1);
     a.round = 0;
-    a.P = P;
-    a.chunk = group / a.P;
+    a.S = S;
     const int ord = table ? order : 0;
     const bool complete = table && table->complete != 0;
 
@@ -734,7 +716,7 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
     const int64_t nbox = (N + 63) / 64;
     SrcRec *rec = (SrcRec *)ws.take((size_t)N * sizeof(SrcRec));
     double *box = (double *)ws.take((size_t)nbox * kBox * sizeof(double));
-    double *sum = (double *)ws.take((size_t)a.P * 4 * N * sizeof(double));
+    double *sum = (double *)ws.take((size_t)2 * S * 4 * N * sizeof(double));
     if (!rec || !box || !sum) return fail(STEPS_EINVAL, "workspace too small for the pairwise path");
     a.rec = rec;
     a.box = box;
@@ -746,7 +728,7 @@ int launch_forces_pairwise(const double *pos, const double *mass, const double *
     if (e == hipSuccess)
         e = dispatch(a.c.n_img, out_pot != nullptr, ord, complete, [&](auto l) { return l.run(a, stream); });
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(finish_kernel, dim3(nb), dim3(256), 0, stream, a.sum, a.P, perm, (int)N, out_acc,
+        hipLaunchKernelGGL(finish_kernel, dim3(nb), dim3(256), 0, stream, a.sum, 2 * S, perm, (int)N, out_acc,
                            out_acc + N, out_acc + 2 * N, out_pot);
         e = hipGetLastError();
     }

@@ -5,7 +5,9 @@
 //
 // Precision: the network keeps FP32 master weights.  Every evaluation uses
 // the weights rounded to BF16; layers 2-4 run on MFMA with BF16 inputs and
-// FP32 accumulation, layers 1 and 5 and all activations in FP32 on the VALU.
+// FP32 accumulation; layer 1 on MFMA with its FP32 inputs split exactly into
+// three BF16 parts (an FP32 layer); layer 5 and all activations in FP32 on
+// the VALU.
 // The backward pass feeds MFMA with BF16 copies of the pre-activation
 // gradients (dW = dZ X^T, dX = W^T dZ); bias gradients and the layer 1 and 5
 // gradients stay FP32.  BF16 roundings are treated as the identity in the
@@ -55,18 +57,14 @@ __device__ __forceinline__ void kpos(int i, int &t, int &h, int &e) {
 
 __device__ void pack_one(int p, float w, Packed *P, PackedT *PT) {
     if (p < OFF_B1) {
+        // W1[r][c]: row r of the layer-1 A fragment, K slots 3c .. 3c+2
         const int r = p >> 1, c = p & 1;
-        int t, h, e;
-        kpos(r, t, h, e);
-        float *q = reinterpret_cast<float *>(&P->L1[h][8 * t + e]);
-        q[c] = (float)(__bf16)w;
+        __bf16 *q = reinterpret_cast<__bf16 *>(&P->A1[r >> 5][r & 31]);
+        q[3 * c] = q[3 * c + 1] = q[3 * c + 2] = (__bf16)w;
     } else if (p < OFF_W[0]) {
-        const int r = p - OFF_B1;
-        int t, h, e;
-        kpos(r, t, h, e);
-        float *q = reinterpret_cast<float *>(&P->L1[h][8 * t + e]);
-        q[2] = w;
-        q[3] = 0.f;
+        int b, v, h;
+        dpos(p - OFF_B1, b, v, h);
+        P->Bias1[h][b][v] = w;
     } else if (p < OFF_W5) {
         int k = 0;
         while (k < 2 && p >= OFF_W[k + 1]) ++k;

@@ -1,6 +1,8 @@
 // Device-side building blocks of the far-image correction network
 // (2 -> 64 -> 64 -> 64 -> 64 -> 2, base-2 SiLU): parameter layout, the packed
 // MFMA operand layout, and the per-wave forward pass over 32 samples.
+// Layers 1-4 run on MFMA (layer 1 on the exact three-part BF16 split of its
+// FP32 inputs, so it stays an FP32 layer), layer 5 on the VALU.
 //
 // MFMA mapping (v_mfma_f32_32x32x16_bf16, FP32 accumulation).  Hidden
 // layers 2-4 are computed transposed, Y^T[64 x 32] = W[64 x 64] X^T[64 x 32],
@@ -48,15 +50,18 @@ constexpr int kFarImages = 1024;      // ... to 1024.5 L
 // Packed inference parameters, laid out so that every lane reads what it
 // needs as consecutive 16-byte chunks from one base address per lane half
 // h (the kernels copy this block to LDS):
-//   A     forward A fragments [layer][M block][K step][lane]
-//   L1    layer 1 row r = 16t + 8(e/4) + 4h + e%4 at [h][8t + e]:
-//         {W1[r][0], W1[r][1], b1[r], 0} (weights BF16-rounded)
+//   A     forward A fragments of layers 2-4 [layer][M block][K step][lane]
+//   A1    layer 1 A fragments [M block][lane]: lane l < 32 holds row
+//         32b + l as {w0, w0, w0, w1, w1, w1, 0, 0} (W1 BF16-rounded), the
+//         other lanes zeros
+//   Bias1 b1[drow(b, v, h)] at [h][b][v]
 //   Bias  b_{k+2}[drow(b, v, h)] at [h][k][b][v]
 //   W5    {W5[0][r], W5[1][r]} for r = drow(b, v, h) at [h][b][v]
 //         (BF16-rounded)
 struct alignas(16) Packed {
     bf16x8 A[3][2][4][64];
-    float4 L1[2][32];
+    bf16x8 A1[2][64];
+    alignas(16) float Bias1[2][2][16];
     alignas(16) float Bias[2][3][2][16];
     float2 W5[2][2][16];
     float b5[4];  // b5[0], b5[1], unused
@@ -91,6 +96,16 @@ __device__ __forceinline__ float silu_grad(float u) {
     return sg * __builtin_fmaf(u * 0.6931471805599453f, 1.0f - sg, 1.0f);
 }
 
+// f = hi + mid + lo with each part BF16 (round to nearest even): each
+// remainder is exact in FP32, and what the three parts leave is below
+// 2^-26 |f|, under FP32 rounding.
+__device__ __forceinline__ void split3(float f, __bf16 &hi, __bf16 &mid, __bf16 &lo) {
+    hi = (__bf16)f;
+    const float r1 = f - (float)hi;
+    mid = (__bf16)r1;
+    lo = (__bf16)(r1 - (float)mid);
+}
+
 // Forward pass for the 32 samples of a wave.  Lanes l and l+32 both carry
 // the features (f1, f2) of sample l%32 and both return its outputs (o0, o1).
 // With CAPTURE, the pre-activations of layers 1..4 (zc, [4][64][32] FP32) and
@@ -102,22 +117,42 @@ __device__ __forceinline__ void forward32(const Packed &P, float f1, float f2, f
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, col = lane & 31;
     bf16x8 xb[4];
-    const float4 *L1 = P.L1[h];
     const float(*Bias)[2][16] = P.Bias[h];
     const float2(*W5)[16] = P.W5[h];
-    // layer 1 on the VALU: this lane computes the 32 units its K slots need
+    // layer 1 on MFMA: K slots 0-5 of lanes 0-31 hold the three-part BF16
+    // splits of f1 and f2 (exact products with the BF16 weights, FP32
+    // accumulation: layer 1 in FP32), the bias enters as the C operand
+    {
+        __bf16 p0, p1, p2, q0, q1, q2;
+        split3(f1, p0, p1, p2);
+        split3(f2, q0, q1, q2);
+        const __bf16 zero = (__bf16)0.f;
+        bf16x8 xin;
+        xin[0] = h ? zero : p0;
+        xin[1] = h ? zero : p1;
+        xin[2] = h ? zero : p2;
+        xin[3] = h ? zero : q0;
+        xin[4] = h ? zero : q1;
+        xin[5] = h ? zero : q2;
+        xin[6] = zero;
+        xin[7] = zero;
+        f32x16 acc1[2];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+        for (int b = 0; b < 2; ++b) {
+            acc1[b] = *reinterpret_cast<const f32x16 *>(&P.Bias1[h][b][0]);
+            acc1[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(P.A1[b][lane], xin, acc1[b], 0, 0, 0);
+        }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int r = 16 * t + 8 * (e >> 2) + 4 * h + (e & 3);
-            const float4 w = L1[8 * t + e];
-            const float z = __builtin_fmaf(w.y, f2, __builtin_fmaf(w.x, f1, w.z));
-            const float a = silu(z);
-            xb[t][e] = (__bf16)a;
-            if (CAPTURE) {
-                zc[r * 32 + col] = z;
-                xc[r * 32 + col] = xb[t][e];
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = drow(b, v, h);
+                const float z = acc1[b][v];
+                xb[2 * b + (v >> 3)][v & 7] = (__bf16)silu(z);
+                if (CAPTURE) {
+                    zc[r * 32 + col] = z;
+                    xc[r * 32 + col] = xb[2 * b + (v >> 3)][v & 7];
+                }
             }
         }
     }

@@ -11,10 +11,10 @@
 namespace steps {
 namespace {
 
-// Largest workspace of one call: the pairwise path at N = 2^20 with one
-// workgroup per meeting (spatial order 16 B, records 32 B and FP64 sums
-// 32 B per particle, boxes, the radix sort's storage) fits with room.
-constexpr size_t kScratchBytes = (size_t)96 << 20;
+// Largest workspace of one call: the pairwise path at N = 2^20 with groups
+// of one part (spatial order 16 B, records 32 B and two slots of FP64 sums
+// 64 B per particle, boxes, the radix sort's storage) fits with room.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
 
 static __device__ __align__(256) char scratch[kScratchBytes];
 
@@ -60,17 +60,17 @@ STEPS_API int steps_cyl_forces_noalloc(const double *pos, const double *mass, co
     int rc = require_device();
     if (rc) return rc;
     clear_error();
-    // as many workgroups per meeting as the device would take, or fewer so
-    // that the workspace fits the static array
-    int P = 16;
-    while (P > 1 && pairwise_bytes_P(N, P) > kScratchBytes) P >>= 1;
-    if (pairwise_bytes_P(N, P) > kScratchBytes)
+    // groups of 16 parts as in steps_cyl_forces, or fewer parts (fewer sum
+    // slots) so that the workspace fits the static array
+    int S = 16;
+    while (S > 1 && pairwise_bytes_S(N, S) > kScratchBytes) S >>= 1;
+    if (pairwise_bytes_S(N, S) > kScratchBytes)
         return fail(STEPS_EINVAL, "N=%lld needs %zu bytes of scratch, above the static %zu", (long long)N,
-                    pairwise_bytes_P(N, P), kScratchBytes);
+                    pairwise_bytes_S(N, S), kScratchBytes);
     void *p = nullptr;
     if ((rc = scratch_on_device(&p))) return rc;
     Workspace ws;
     ws.base = (char *)p;
     ws.size = kScratchBytes;
-    return launch_forces_pairwise(pos, mass, eps, N, L, n_img, nullptr, 0, out_acc, out_pot, ws, stream, P);
+    return launch_forces_pairwise(pos, mass, eps, N, L, n_img, nullptr, 0, out_acc, out_pot, ws, stream, S);
 }
