@@ -76,9 +76,9 @@ REACTION_FLOPS = 9
 
 
 def pairwise_group(N):
-    """Particles per group of the exact pairwise path: 16 parts of 256 up to
-    2^21 particles, else 8."""
-    return 256 * (16 if N <= (1 << 21) else 8)
+    """Particles per group of the exact pairwise path: 16 parts of 64 (one
+    particle per lane of a one-wave workgroup) up to 2^21 particles, else 8."""
+    return 64 * (16 if N <= (1 << 21) else 8)
 
 
 def pairwise_evaluations(N):

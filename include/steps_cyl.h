@@ -121,7 +121,8 @@ typedef struct steps_cyl_table steps_cyl_table;   /* opaque; owns device memory 
  * set of (i, j)), so the reaction is the action with dx, dy and F_z negated
  * (F_z keeps its sign where both particles take the minimum image -L/2).
  * Arithmetic: pair separations and the z wrap in FP64, FP32 pair terms,
- * FP64 sums.  Groups of 1024 particles in spatial order meet in a fixed
+ * FP64 sums.  Groups of 64 S particles in spatial order (S parts of 64,
+ * one particle per lane of a one-wave workgroup) meet in a fixed
  * round-robin tournament (one launch per round, no atomics), so repeated
  * calls are bitwise equal.  Total momentum is conserved to the rounding of
  * the sums.  Workspace (stream-ordered here; see steps_cyl_forces_ws): 32
@@ -343,8 +344,9 @@ int steps_cyl_mlp_load(const char *path, steps_cyl_mlp **out);
  * away; h_i + h_j below that is assumed).  The learned pair term is odd in
  * the separation (R_z odd in d, R_rho even), so, as in steps_cyl_forces,
  * every unordered pair is evaluated once and applied to both particles, with
- * FP64 sums: groups of 128 particles meet in the round-robin tournament of
- * steps_cyl_forces (no atomics; repeated calls are bitwise equal).
+ * FP64 sums: groups of 1024 particles (8 sub-groups of 128) meet in the
+ * round-robin tournament of steps_cyl_forces (no atomics; repeated calls
+ * are bitwise equal).
  * Workspace about 80 bytes per particle (records, sums, spatial order).
  */
 int steps_cyl_forces_learned(const double *pos, const double *mass, const double *eps,

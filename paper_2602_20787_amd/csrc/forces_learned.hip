@@ -359,10 +359,14 @@ int launch_forces_learned(const double *pos, const double *mass, const double *e
 // slot has one writer per launch and every sum is a plain read-modify-write
 // in an order fixed by N.  A launch holds kSubs^2 G'/2 workgroups of equal
 // size, so one slow meeting (a near pair of groups, with many pairs outside
-// the network's domain) is a small part of it.  The reactions on a source
-// are summed over the 32 lanes of its half-wave, then over the 4 waves in
-// LDS.  Both sides are summed in FP64 (sources in spatial order would cost
-// FP32 partials their cancellation).
+// the network's domain) is a small part of it.  A wave walks the sources in
+// blocks of 64, 32 steps per block: at step u lane (h, c) takes source
+// 32h + (c + u) mod 32 of the block, so the 64 lanes meet 64 different
+// sources and each source meets the wave's 32 targets over the 32 steps.
+// The reaction on a source is then summed in an FP64 LDS slot per wave that
+// the lanes update in turn (no cross-lane reduction), and the 4 waves'
+// slots are added in order at the end.  Both sides are summed in FP64
+// (sources in spatial order would cost FP32 partials their cancellation).
 namespace {
 
 constexpr int kOwn = 128;  // particles per sub-group, one per wave column
@@ -413,7 +417,7 @@ template <bool POT, bool REACT>
 __global__ __launch_bounds__(kBlock, 2) void forces_learned_pairwise_kernel(PairwiseLearnedArgs pa) {
     __shared__ mlp::Packed P;
     __shared__ SrcRec tile[kOwn];
-    __shared__ double jpart[kBlock / 64][kOwn][4];
+    __shared__ double jpart[kBlock / 64][4][kOwn];  // per wave, component, source
     const LearnedArgs &a = pa.la;
     const int meet = blockIdx.x / (kSubs * kSubs);
     const int si = (blockIdx.x / kSubs) % kSubs, sj = blockIdx.x % kSubs;
@@ -457,80 +461,81 @@ __global__ __launch_bounds__(kBlock, 2) void forces_learned_pairwise_kernel(Pair
     const int base = sb * kOwn;
     const int cnt = max(0, min(kOwn, pa.N - base));  // 0: an empty sub-group of the self meeting
     if (tid < cnt) tile[tid] = pa.rec[base + tid];
-    __syncthreads();  // the tile and the parameters are in LDS
-    for (int s = 0; s < cnt; s += 2) {
-        const bool live = (s + h) < cnt;
-        const int js = live ? (s + h) : s;
-        const SrcRec src = tile[js];
-        const bool self = !REACT && (base + js == t);
-        PairState q = pair_state<POT>(src, self, live, xi, yi, zi, hi, a);
-        const float g1 = __shfl_xor(q.f1, 32), g2 = __shfl_xor(q.f2, 32);
-        const float fa1 = h ? g1 : q.f1, fa2 = h ? g2 : q.f2;
-        const float fb1 = h ? q.f1 : g1, fb2 = h ? q.f2 : g2;
-        int poff = 0;
-        asm volatile("" : "+v"(poff));
-        const mlp::Packed &Pl = *reinterpret_cast<const mlp::Packed *>(
-            reinterpret_cast<const char *>(&P) + poff);
-        float oa0, oa1, ob0, ob1;
-        mlp::forward32<false>(Pl, fa1, fa2, oa0, oa1, nullptr, nullptr);
-        mlp::forward32<false>(Pl, fb1, fb2, ob0, ob1, nullptr, nullptr);
-        const float o0 = h ? ob0 : oa0, o1 = h ? ob1 : oa1;
-        const float mz = __builtin_fmaf(q.sc, o0, q.bz);
-        float Rz = (q.d > 0.f) ? mz : ((q.d < 0.f) ? -mz : 0.f);
-        float Rr = __builtin_fmaf(q.sc, o1, q.br);
-        if (!q.inside) {
-            Rz = 0.f;
-            Rr = 0.f;
-        }
-        uint64_t outside = __ballot(q.band && active);
-        while (outside) {
-            const int c = __builtin_ctzll(outside);
-            outside &= outside - 1;
-            const float dc = __shfl(q.d * a.invLf, c), rc = __shfl(q.r, c);
-            float tz, tr;
-            band_cooperative(dc, rc, tz, tr);
-            if (lane == c) {
-                Rz = tz;
-                Rr = tr;
+    if (REACT) {
+        double *jz0 = &jpart[0][0][0];
+        for (int q = tid; q < (kBlock / 64) * 4 * kOwn; q += kBlock) jz0[q] = 0.0;
+    }
+    __syncthreads();  // the tile, the parameters and the cleared slots are in LDS
+    for (int s0 = 0; s0 < cnt; s0 += 64) {
+        for (int u = 0; u < 32; ++u) {
+            const int jr = s0 + 32 * h + ((col + u) & 31);
+            const bool live = jr < cnt;
+            const int js = live ? jr : 0;  // a dead lane reads a real record and adds nothing
+            const SrcRec src = tile[js];
+            const bool self = !REACT && (base + js == t);
+            PairState q = pair_state<POT>(src, self, live, xi, yi, zi, hi, a);
+            const float g1 = __shfl_xor(q.f1, 32), g2 = __shfl_xor(q.f2, 32);
+            const float fa1 = h ? g1 : q.f1, fa2 = h ? g2 : q.f2;
+            const float fb1 = h ? q.f1 : g1, fb2 = h ? q.f2 : g2;
+            int poff = 0;
+            asm volatile("" : "+v"(poff));
+            const mlp::Packed &Pl = *reinterpret_cast<const mlp::Packed *>(
+                reinterpret_cast<const char *>(&P) + poff);
+            float oa0, oa1, ob0, ob1;
+            mlp::forward32<false>(Pl, fa1, fa2, oa0, oa1, nullptr, nullptr);
+            mlp::forward32<false>(Pl, fb1, fb2, ob0, ob1, nullptr, nullptr);
+            const float o0 = h ? ob0 : oa0, o1 = h ? ob1 : oa1;
+            const float mz = __builtin_fmaf(q.sc, o0, q.bz);
+            float Rz = (q.d > 0.f) ? mz : ((q.d < 0.f) ? -mz : 0.f);
+            float Rr = __builtin_fmaf(q.sc, o1, q.br);
+            if (!q.inside) {
+                Rz = 0.f;
+                Rr = 0.f;
             }
-        }
-        const float rinv = q.rho > 0.f ? __builtin_amdgcn_rcpf(q.rho) : 0.f;
-        const double Seff = (double)__builtin_fmaf(-Rr * a.invL2f, rinv, q.S);
-        const double Fzeff = (double)__builtin_fmaf(-Rz, a.invL2f, q.Fz);
-        const double Pn = (double)q.Pn;
-        const double mj = (double)q.m;  // 0 past the tile's end
-        sx = __builtin_fma(mj * Seff, (double)q.dx, sx);
-        sy = __builtin_fma(mj * Seff, (double)q.dy, sy);
-        sz = __builtin_fma(mj, Fzeff, sz);
-        if (POT) sp = __builtin_fma(mj, Pn, sp);
-        if (REACT) {
-            // the source sees -dx, -dy and -d, except where |d| = L/2 up to
-            // rounding and its own minimum image has the sign of d
-            double fz = Fzeff;
-            if (__builtin_fabsf(q.d) >= pa.tie32) {
-                const double d64 = min_image(zi - src.z, a.L, a.invL);
-                if (__builtin_fabs(__builtin_fabs(d64) - a.halfL) <= pa.tie) {
-                    const double dji = min_image(src.z - zi, a.L, a.invL);
-                    if ((dji < 0.0) == (d64 < 0.0)) fz = -Fzeff;
+            uint64_t outside = __ballot(q.band && active);
+            while (outside) {
+                const int c = __builtin_ctzll(outside);
+                outside &= outside - 1;
+                const float dc = __shfl(q.d * a.invLf, c), rc = __shfl(q.r, c);
+                float tz, tr;
+                band_cooperative(dc, rc, tz, tr);
+                if (lane == c) {
+                    Rz = tz;
+                    Rr = tr;
                 }
             }
-            const double w = live ? (double)mi : 0.0;
-            double jx = w * Seff * (double)q.dx, jy = w * Seff * (double)q.dy, jz = w * fz;
-            double jp = POT ? w * Pn : 0.0;
-            // sum over the 32 targets of this half
-#pragma unroll
-            for (int off = 16; off >= 1; off >>= 1) {
-                jx += __shfl_xor(jx, off);
-                jy += __shfl_xor(jy, off);
-                jz += __shfl_xor(jz, off);
-                if (POT) jp += __shfl_xor(jp, off);
+            const float rinv = q.rho > 0.f ? __builtin_amdgcn_rcpf(q.rho) : 0.f;
+            const double Seff = (double)__builtin_fmaf(-Rr * a.invL2f, rinv, q.S);
+            const double Fzeff = (double)__builtin_fmaf(-Rz, a.invL2f, q.Fz);
+            const double Pn = (double)q.Pn;
+            const double mj = (double)q.m;  // 0 for a dead lane
+            sx = __builtin_fma(mj * Seff, (double)q.dx, sx);
+            sy = __builtin_fma(mj * Seff, (double)q.dy, sy);
+            sz = __builtin_fma(mj, Fzeff, sz);
+            if (POT) sp = __builtin_fma(mj, Pn, sp);
+            if (REACT && live) {
+                // the source sees -dx, -dy and -d, except where |d| = L/2 up
+                // to rounding and its own minimum image has the sign of d
+                double fz = Fzeff;
+                if (__builtin_fabsf(q.d) >= pa.tie32) {
+                    const double d64 = min_image(zi - src.z, a.L, a.invL);
+                    if (__builtin_fabs(__builtin_fabs(d64) - a.halfL) <= pa.tie) {
+                        const double dji = min_image(src.z - zi, a.L, a.invL);
+                        if ((dji < 0.0) == (d64 < 0.0)) fz = -Fzeff;
+                    }
+                }
+                const double w = (double)mi;  // 0 for an empty target slot
+                const double wS = w * Seff;
+                double *jw = &jpart[wave][0][js];
+                jw[0] = __builtin_fma(wS, (double)q.dx, jw[0]);
+                jw[kOwn] = __builtin_fma(wS, (double)q.dy, jw[kOwn]);
+                jw[2 * kOwn] = __builtin_fma(w, fz, jw[2 * kOwn]);
+                if (POT) jw[3 * kOwn] = __builtin_fma(w, Pn, jw[3 * kOwn]);
             }
-            if (col == 0 && live) {
-                jpart[wave][s + h][0] = jx;
-                jpart[wave][s + h][1] = jy;
-                jpart[wave][s + h][2] = jz;
-                jpart[wave][s + h][3] = jp;
-            }
+            // the next step's lanes read the slots this step wrote: a
+            // compiler barrier keeps the steps' LDS accesses in program
+            // order (the wave's LDS operations complete in issue order)
+            asm volatile("" ::: "memory");
         }
     }
     if (REACT) {
@@ -542,7 +547,7 @@ __global__ __launch_bounds__(kBlock, 2) void forces_learned_pairwise_kernel(Pair
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (k == 3 && !POT) continue;
-                const double v = (jpart[0][tid][k] + jpart[1][tid][k]) + (jpart[2][tid][k] + jpart[3][tid][k]);
+                const double v = (jpart[0][k][tid] + jpart[1][k][tid]) + (jpart[2][k][tid] + jpart[3][k][tid]);
                 double *p = pa.acc + ((int64_t)(kSubs + si) * 4 + k) * pa.N + jj;
                 *p = (k == 3) ? *p + v : *p - v;
             }

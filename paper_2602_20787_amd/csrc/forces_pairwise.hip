@@ -12,10 +12,9 @@
 //
 // Layout.  The particles are put in spatial (Morton) order and staged as
 // 32-byte records {x, y, z wrapped, m, h}, with a bounding box per run of 64
-// records.  A part is 64 kR consecutive records (kR = 4 particles per lane,
-// 2 with a table); a group is S parts (S = 16 up to 2^21 particles, else 8;
-// 8 with a table).  Each particle has 2S slots of FP64 sums (x, y, z,
-// potential).
+// records.  A part is 64 kR consecutive records (kR = 1 particle per lane);
+// a group is S parts (S = 16 up to 2^21 particles, else 8; 8 with a table).
+// Each particle has 2S slots of FP64 sums (x, y, z, potential).
 //
 // Schedule (bitwise deterministic, no atomics).  A first launch pairs every
 // group with itself (one-sided, every ordered pair, the self pair skipped)
@@ -40,9 +39,9 @@
 // the sum of the largest softenings, no axial separation near L/2) skips the
 // softening and half-period screens and the per-pair minimum image; the pair
 // arithmetic is the same either way.  One-wave workgroups need no barrier
-// between waves, and a workgroup's memory traffic (its part's records and
-// both parts' sums) is shared by 4096 (1024) pairs per particle pair of
-// parts, twice what a 1024-particle workgroup streaming 64 sources moves.
+// between waves.  Small register sets let several of them share a SIMD,
+// which hides the latency of the transcendentals (17 reciprocal square
+// roots per pair) and of the LDS traffic behind the other waves' work.
 #include <algorithm>
 
 #include "common.h"
@@ -55,11 +54,19 @@ namespace steps {
 namespace {
 
 constexpr int kThreads = 64;  // one wave
-// particles per lane: 4 for the exact pair (the reaction's LDS update is
-// shared by more pairs); 2 with a table, whose gathers want the occupancy
-// that the smaller register set gives
-constexpr int particles_per_thread(int torder) { return torder > 0 ? 2 : 4; }
-constexpr int kMaxR = 4;
+// Particles per lane and waves per SIMD.  The exact pair: one particle per
+// lane in at most 96 VGPRs, 5 waves per SIMD.  Measured per call at
+// N = 2^20, |n| <= 8 with the potential (ms): 1 per lane at 4, 5, 6 and 8
+// waves 1994, 1891, 1895 and 1918; 2 per lane at 2 and 3 waves 2067 and
+// 2110; 4 per lane at 2 waves (256 VGPRs) 2182.  The extra VALU work of
+// one particle per lane (139 instructions per pair in the far loop against
+// 134.5 with four, for the reaction's LDS update and the loop) costs less
+// than the latency the extra waves hide.  With a table, one per lane and a
+// bound of 4 waves (80-83 VGPRs, so 5-6 waves fit): CIC 1436 and TSC 2042 ms,
+// against 1473 and 2200 with 2 per lane at 3 waves and 1441 and 2075 with
+// the bound at 6 waves.
+constexpr int particles_per_thread(int) { return 1; }
+constexpr int waves_per_simd(int torder) { return torder > 0 ? 4 : 5; }
 constexpr int kSub = 64;    // sources per sub-tile (one rotation)
 constexpr int kBox = 8;     // doubles per 64-record box
 
@@ -467,7 +474,7 @@ __device__ __forceinline__ void near_pass(const PairwiseArgs &a, const Owned<kR>
 // a.round) or of one group's meeting with itself: part i of group a against
 // part j of group b.
 template <int NIMG, bool POT, int TORDER, bool COMPLETE, bool REACT>
-__global__ __launch_bounds__(kThreads, TORDER > 0 ? 3 : 2) void forces_pairwise_kernel(PairwiseArgs a) {
+__global__ __launch_bounds__(kThreads, waves_per_simd(TORDER)) void forces_pairwise_kernel(PairwiseArgs a) {
     constexpr int kR = particles_per_thread(TORDER);
     constexpr int kPart = 64 * kR;  // particles per part
     __shared__ Stage<kR> st;
@@ -626,12 +633,13 @@ struct Launcher {
 template <class F>
 auto dispatch(int n_img, bool pot, int order, bool complete, F &&f) {
     if (order == 0) {
+        // image counts unrolled at compile time where the unrolled loop fits
+        // the register budget; the others (the compiler spills the unrolled
+        // 1-, 2- and 4-image forms with the potential and the 4-image form
+        // without) take the run-time loop, which fits
         if (pot) {
             switch (n_img) {
                 case 0: return f(Launcher<0, true, 0, false>{});
-                case 1: return f(Launcher<1, true, 0, false>{});
-                case 2: return f(Launcher<2, true, 0, false>{});
-                case 4: return f(Launcher<4, true, 0, false>{});
                 case 8: return f(Launcher<8, true, 0, false>{});
                 default: return f(Launcher<-1, true, 0, false>{});
             }
@@ -640,7 +648,6 @@ auto dispatch(int n_img, bool pot, int order, bool complete, F &&f) {
             case 0: return f(Launcher<0, false, 0, false>{});
             case 1: return f(Launcher<1, false, 0, false>{});
             case 2: return f(Launcher<2, false, 0, false>{});
-            case 4: return f(Launcher<4, false, 0, false>{});
             case 8: return f(Launcher<8, false, 0, false>{});
             default: return f(Launcher<-1, false, 0, false>{});
         }
@@ -655,12 +662,11 @@ auto dispatch(int n_img, bool pot, int order, bool complete, F &&f) {
 
 }  // namespace
 
-// Parts per group of a pairwise call.  More parts make a launch hold more,
-// shorter workgroups (its tail is one of them) at the price of 2 sum slots
-// (64 B) per particle each.  Measured per call at N = 2^20: S = 4, 8, 16 took
-// 2341, 2231 and 2181 ms (exact), and S = 8, 16 CIC 1465 and 1503 ms (the
-// table kernel's parts are half as large); at N = 2^21 S = 8, 16 took 8681
-// and 8559 ms.  Above 2^21 particles a call has enough meetings with S = 8
+// Parts per group of a pairwise call.  More parts make a launch hold more
+// workgroups at the price of 2 sum slots (64 B) per particle each.  Measured
+// per call at N = 2^20 with parts of 64: S = 16 and 32 took 1891 and 1894 ms
+// (exact), S = 8, 16 and 32 CIC 1441, 1461 and 1464 ms and TSC 2075, 2089
+// and 2085 ms.  Above 2^21 particles a call has enough meetings with S = 8
 // and the slots would grow past 2 GiB.
 int pairwise_parts(int64_t N, const steps_cyl_table *table) {
     if (table) return 8;
