@@ -52,8 +52,8 @@ PEAK_FP32_UNPACKED = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 # what the counter reads for a 256 MiB copy
 # (profiles/forces_pairwise_N1M_nimg8_counters.md).  Valid only for the
 # kernel sources they were measured on (hash below); None until measured.
-TRAFFIC_EXACT_N1M = {"bytes": 3.1667e11, "fetch_scale": 1.99974, "write_scale": 1.0,
-                     "sources_sha256_16": "172db70680025d97"}
+TRAFFIC_EXACT_N1M = {"bytes": 1.3253e12, "fetch_scale": 1.99974, "write_scale": 1.0,
+                     "sources_sha256_16": "c13a2cf9e317bbd3"}
 TRAFFIC_SOURCES = ["forces_pairwise.hip", "pair_fp32.h", "pair_f64.h", "target_order.hip"]
 
 

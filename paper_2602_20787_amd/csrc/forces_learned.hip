@@ -122,7 +122,7 @@ __device__ __forceinline__ PairState pair_state(const SrcRec &src, bool self, bo
 }
 
 template <bool POT, bool COMP>
-__global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
+__global__ __launch_bounds__(kBlock, 3) void forces_learned_kernel(LearnedArgs a) {
     __shared__ mlp::Packed P;
     __shared__ SrcRec tile[kTile];
     mlp::load_packed(&P, a.P);
@@ -177,6 +177,11 @@ __global__ __launch_bounds__(kBlock) void forces_learned_kernel(LearnedArgs a) {
                     reinterpret_cast<const char *>(&P) + poff);
                 float oa0, oa1, ob0, ob1;
                 mlp::forward32<false>(Pl, fa1, fa2, oa0, oa1, nullptr, nullptr);
+                // the two tiles one after the other: one tile's registers
+                // let 3 waves share a SIMD, and the other waves hide the
+                // MFMA and transcendental latency that interleaving the
+                // tiles would
+                __builtin_amdgcn_sched_barrier(0);
                 mlp::forward32<false>(Pl, fb1, fb2, ob0, ob1, nullptr, nullptr);
                 const float o0 = h ? ob0 : oa0, o1 = h ? ob1 : oa1;
                 const float mz = __builtin_fmaf(q.sc, o0, q.bz);
@@ -414,7 +419,7 @@ __global__ void lp_finish_kernel(const double *acc, const int *perm, int N, floa
 // Workgroup (i, j) of one meeting (REACT: the groups of tournament round
 // pa.round) or of one group's meeting with itself.
 template <bool POT, bool REACT>
-__global__ __launch_bounds__(kBlock, 2) void forces_learned_pairwise_kernel(PairwiseLearnedArgs pa) {
+__global__ __launch_bounds__(kBlock, 3) void forces_learned_pairwise_kernel(PairwiseLearnedArgs pa) {
     __shared__ mlp::Packed P;
     __shared__ SrcRec tile[kOwn];
     __shared__ double jpart[kBlock / 64][4][kOwn];  // per wave, component, source
@@ -483,6 +488,8 @@ __global__ __launch_bounds__(kBlock, 2) void forces_learned_pairwise_kernel(Pair
                 reinterpret_cast<const char *>(&P) + poff);
             float oa0, oa1, ob0, ob1;
             mlp::forward32<false>(Pl, fa1, fa2, oa0, oa1, nullptr, nullptr);
+            // one tile after the other (3 waves per SIMD, as the per-target kernel)
+            __builtin_amdgcn_sched_barrier(0);
             mlp::forward32<false>(Pl, fb1, fb2, ob0, ob1, nullptr, nullptr);
             const float o0 = h ? ob0 : oa0, o1 = h ? ob1 : oa1;
             const float mz = __builtin_fmaf(q.sc, o0, q.bz);

@@ -13,7 +13,8 @@ load); the homogeneous-cylinder pull of the matching height is compensated.
 Every --check-every steps the axial momentum and the force error on sampled
 targets against the FP64 GPU reference (|n| <= 1024 for the learned and band
 modes, n_img for exact, 4096 for complete and tree) are reported.  Prints one line
-per step and a JSON summary.
+per step and a JSON summary.  --stop-after K runs the first K steps of the
+schedule only.
 
     python -m paper_2602_20787_amd.simulate --N 131072 --steps 64
 """
@@ -47,6 +48,8 @@ def main(argv=None):
     ap.add_argument("--check-targets", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--net", default=NET)
+    ap.add_argument("--stop-after", type=int, default=None,
+                    help="run only the first K steps of the --steps schedule")
     args = ap.parse_args(argv)
 
     import numpy as np
@@ -104,6 +107,7 @@ def main(argv=None):
     def pz():
         return float((m * mom[2]).sum()), float((m * mom[2].abs()).sum())
 
+    print(f"[sim] N={args.N} mode={args.mode}: load ready, initial forces", flush=True)
     t0 = time.perf_counter()
     acc = forces()
     torch.cuda.synchronize()
@@ -114,7 +118,8 @@ def main(argv=None):
     print(f"[sim] N={args.N} mode={args.mode} step 0 a={args.a0:.4f} force err max {e0[0]:.2e}",
           flush=True)
     pz_max_ratio = 0.0
-    for k in range(args.steps):
+    n_run = args.steps if args.stop_after is None else max(0, min(args.steps, args.stop_after))
+    for k in range(n_run):
         par = sc.kdk_params(grid[k], grid[k + 1], H0, Om, OL, R_cyl=R, rho0=rho0,
                             n_img=args.n_img, net=net, table=table, table_order=args.table_order,
                             tree=tree, theta=args.theta, tree_shift=frames.random() * L,
@@ -125,7 +130,7 @@ def main(argv=None):
         ratio = abs(P) / Ps if Ps > 0 else 0.0
         pz_max_ratio = max(pz_max_ratio, ratio)
         line = f"[sim] step {k + 1} a={grid[k + 1]:.4f} P_z={P:+.3e} |P_z|/sum m|p_z|={ratio:.2e}"
-        if (k + 1) % args.check_every == 0 or k + 1 == args.steps:
+        if (k + 1) % args.check_every == 0 or k + 1 == n_run:
             ek = check(acc)
             checks.append({"step": k + 1, "a": float(grid[k + 1]), "max_rel_err": ek[0],
                            "median_rel_err": ek[1], "pz_ratio": ratio})
@@ -134,7 +139,8 @@ def main(argv=None):
     disp = (pos - torch.from_numpy(p.pos).to(dev))
     disp[2] -= torch.round(disp[2] / L) * L
     summary = {
-        "N": args.N, "steps": args.steps, "mode": args.mode, "a0": args.a0, "a1": args.a1,
+        "N": args.N, "steps": args.steps, "steps_run": n_run, "mode": args.mode, "a0": args.a0,
+        "a1": args.a1, "a_reached": float(grid[n_run]),
         "wall_s": round(time.perf_counter() - t0, 2),
         "max_pz_ratio": pz_max_ratio,
         "rms_displacement": float(disp.pow(2).sum(dim=0).mean().sqrt()),

@@ -51,3 +51,19 @@ def test_profiling_driver_runs_each_path(capsys, argv):
     row = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
     assert row["path"] == argv[1] and row["N"] == 8192 and len(row["ms"]) == 2
     assert all(ms > 0 for ms in row["ms"])
+
+
+def test_stop_after_runs_a_prefix_of_the_schedule(sim, capsys):
+    # the first 3 of 6 steps: the same step sizes and, with deterministic
+    # forces and kicks, the same state as the full run at step 3
+    base = ["--N", "4096", "--steps", "6", "--mode", "exact", "--check-every", "3",
+            "--check-targets", "256", "--a1", "0.05"]
+    assert sim.main(base) == 0
+    full = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert sim.main(base + ["--stop-after", "3"]) == 0
+    part = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert part["steps_run"] == 3 and full["steps_run"] == 6
+    assert part["a_reached"] == pytest.approx(full["checks"][1]["a"], rel=1e-15)
+    assert part["checks"][-1]["step"] == 3
+    assert part["checks"][-1]["max_rel_err"] == full["checks"][1]["max_rel_err"]
+    assert part["checks"][-1]["median_rel_err"] == full["checks"][1]["median_rel_err"]
