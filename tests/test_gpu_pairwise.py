@@ -135,3 +135,25 @@ def test_rejects_a_target_list(sc):
     with pytest.raises(sc.StepsError):
         sc.steps_cyl_forces_ex(dev(p.pos), dev(p.mass), dev(p.eps), p.L, 8, targets=t,
                                mode=sc.STEPS_SUM_PAIRWISE)
+
+
+def test_above_two_million_groups_hold_eight_parts(sc):
+    # above 2^21 particles a group holds 8 parts instead of 16 (an odd number
+    # of groups here, and a ragged last part): sampled targets against the
+    # FP64 GPU reference and the oracle, total momentum as above
+    N = (1 << 21) + 37
+    p = synth.cylinder_load(N, seed=21)
+    pos, m, e = dev(p.pos), dev(p.mass), dev(p.eps)
+    a, pot = sc.steps_cyl_forces(pos, m, e, p.L, 8)
+    tg = synth.target_sample(N, 512, seed=5)
+    t = torch.from_numpy(tg).to(pos.device)
+    ref, ref_pot = sc.steps_cyl_forces_f64(pos, m, e, p.L, 8, targets=t)
+    torch.cuda.synchronize()
+    a_s, r = a[:, t].double().cpu().numpy(), ref.cpu().numpy()
+    check(a_s, pot[t].double().cpu().numpy(), r, ref_pot.cpu().numpy())
+    a_o, p_o = oracle.forces(p.pos, p.mass, p.eps, p.L, 8, targets=tg[:32])
+    check(a_s[:, :32], pot[t[:32]].double().cpu().numpy(), a_o, p_o)
+    a_all = a.double().cpu().numpy()
+    mom = np.abs((p.mass[None, :] * a_all).sum(axis=1)) / (p.mass[None, :] * np.abs(a_all)).sum(axis=1)
+    print("momentum residual", mom)
+    assert mom.max() <= 1e-6
