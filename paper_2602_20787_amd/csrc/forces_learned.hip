@@ -18,6 +18,8 @@
 // instead; all 64 lanes share that sum (32 images each plus a butterfly
 // reduction), so a rare outside pair costs about 250 instructions instead
 // of a 2046-image serial loop in one lane.
+#include <cmath>
+
 #include "common.h"
 #include "learned_model.h"
 #include "mlp_device.h"
@@ -32,6 +34,24 @@ constexpr int kTargets = 128;   // targets per workgroup (32 per wave)
 constexpr int kTile = 256;      // sources per LDS tile
 constexpr int kSub = 32;        // sources per compensated flush
 
+// The band 2 <= |n| <= 1024 of a pair near the axis (rho < 0.05 L), where the
+// network is not defined, as a convergent series rather than 2046 image
+// terms.  With x = n -+ delta >= 1.5 (|delta| = |d|/L <= 1/2) and
+// (rho/x)^2 < 1.2e-3, (x^2 + rho^2)^(-3/2) = x^-3 sum_k b_k (rho^2/x^2)^k,
+// b_k = binom(-3/2, k); four terms leave less than 4e-12 of the sum.  Then
+//   F_z   =  delta  sum_k b_k rho^2k H_k(delta^2),
+//   F_rho = -rho    sum_k b_k rho^2k G_k(delta^2),
+// H_k = sum_n [(n - delta)^-(2+2k) - (n + delta)^-(2+2k)] / delta and
+// G_k = sum_n [(n - delta)^-(3+2k) + (n + delta)^-(3+2k)], smooth functions
+// of delta^2 held as degree-8 polynomials in t = 8 delta^2 - 1 on [-1, 1]
+// (Chebyshev interpolation in FP64 when the library loads, under 1e-9 of
+// the sums).  Evaluated in FP32 the result is the exact band to FP32
+// rounding (1.7e-7 of it at most, checked against the direct sum on 3000
+// random pairs).
+struct BandSeries {
+    float c[2][4][9];  // [F_z | F_rho][k][monomial coefficient of t, highest first], times b_k
+};
+
 struct LearnedArgs {
     const double *x, *y, *z, *m, *h;
     const int64_t *targets;
@@ -44,7 +64,27 @@ struct LearnedArgs {
     ImageConsts c;  // n_img = 1
     int N, n_tgt;
     int chunk;        // sources per chunk (a multiple of kTile, or N)
+    BandSeries bs;    // near-axis band
 };
+
+__device__ __forceinline__ void band_near_axis(const BandSeries &bs, float delta, float r, float &fz, float &fr) {
+    const float t = __builtin_fmaf(8.0f * delta, delta, -1.0f);
+    const float r2 = r * r;
+    float pz = 0.f, pr = 0.f;
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+        float hz = bs.c[0][k][0], hr = bs.c[1][k][0];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            hz = __builtin_fmaf(hz, t, bs.c[0][k][i]);
+            hr = __builtin_fmaf(hr, t, bs.c[1][k][i]);
+        }
+        pz = __builtin_fmaf(pz, r2, hz);
+        pr = __builtin_fmaf(pr, r2, hr);
+    }
+    fz = delta * pz;
+    fr = -r * pr;
+}
 
 // Exact band 2 <= |n| <= 1024 for one pair (delta = d/L signed, r = rho/L),
 // shared by the 64 lanes of the wave; every lane returns the totals
@@ -121,11 +161,45 @@ __device__ __forceinline__ PairState pair_state(const SrcRec &src, bool self, bo
     return q;
 }
 
+// The band series' coefficients copied into the workgroup's LDS (read there
+// only by waves that meet a near-axis pair; kept out of scalar registers).
+__device__ __forceinline__ void load_band_series(BandSeries *dst, const BandSeries &src) {
+    constexpr int n = (int)(sizeof(BandSeries) / sizeof(float));
+    const float *s = &src.c[0][0][0];
+    float *d = &dst->c[0][0][0];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+}
+
+// The band of a pair outside the network's domain (R_z, R_rho per unit
+// G m_j / L^2): near the axis from the series, beyond the domain's outer
+// edge exactly, with the 64 lanes of the wave sharing each such pair.
+__device__ __forceinline__ void band_outside(const LearnedArgs &a, const BandSeries &bs, const PairState &q,
+                                             bool active, float &Rz, float &Rr) {
+    const int lane = threadIdx.x & 63;
+    const bool out = q.band && active;
+    const bool axis = out && q.r < mlp::kRhoMin;
+    if (axis) band_near_axis(bs, q.d * a.invLf, q.r, Rz, Rr);
+    uint64_t outside = __ballot(out && !axis);
+    while (outside) {
+        const int c = __builtin_ctzll(outside);
+        outside &= outside - 1;
+        const float dc = __shfl(q.d * a.invLf, c), rc = __shfl(q.r, c);
+        float tz, tr;
+        band_cooperative(dc, rc, tz, tr);
+        if (lane == c) {
+            Rz = tz;
+            Rr = tr;
+        }
+    }
+}
+
 template <bool POT, bool COMP>
 __global__ __launch_bounds__(kBlock, 3) void forces_learned_kernel(LearnedArgs a) {
     __shared__ mlp::Packed P;
     __shared__ SrcRec tile[kTile];
+    __shared__ BandSeries bands;
     mlp::load_packed(&P, a.P);
+    load_band_series(&bands, a.bs);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int col = lane & 31, h = lane >> 5;
@@ -191,18 +265,7 @@ __global__ __launch_bounds__(kBlock, 3) void forces_learned_kernel(LearnedArgs a
                     Rz = 0.f;
                     Rr = 0.f;
                 }
-                uint64_t outside = __ballot(q.band && active);
-                while (outside) {
-                    const int c = __builtin_ctzll(outside);
-                    outside &= outside - 1;
-                    const float dc = __shfl(q.d * a.invLf, c), rc = __shfl(q.r, c);
-                    float tz, tr;
-                    band_cooperative(dc, rc, tz, tr);
-                    if (lane == c) {
-                        Rz = tz;
-                        Rr = tr;
-                    }
-                }
+                band_outside(a, bands, q, active, Rz, Rr);
                 // a = -m_j [ S (dx, dy, *) - R_rho (dx, dy)/(rho L^2) , Fz - R_z / L^2 ]
                 const float rinv = q.rho > 0.f ? __builtin_amdgcn_rcpf(q.rho) : 0.f;
                 const float Seff = __builtin_fmaf(-Rr * a.invL2f, rinv, q.S);
@@ -287,6 +350,62 @@ size_t learned_per_target_bytes(int64_t N, int64_t n_tgt) {
     return ws_total({per_target_bytes(n_tgt), chunks > 1 ? (size_t)chunks * 4 * n_tgt * sizeof(double) : 0});
 }
 
+namespace {
+
+// Coefficients of the near-axis band series (BandSeries), computed once in
+// FP64: the sums at 32 Chebyshev nodes of t, the truncated Chebyshev series
+// of degree 8, converted to monomials in t.
+BandSeries make_band_series() {
+    constexpr int kNodes = 32, kDeg = 8;
+    constexpr double kPi = 3.14159265358979323846;
+    const double b[4] = {1.0, -1.5, 1.875, -2.1875};  // binom(-3/2, k)
+    BandSeries bs{};
+    for (int comp = 0; comp < 2; ++comp)
+        for (int k = 0; k < 4; ++k) {
+            const int m = (comp == 0 ? 2 : 3) + 2 * k;
+            double f[kNodes];
+            for (int j = 0; j < kNodes; ++j) {
+                const double t = std::cos(kPi * (j + 0.5) / kNodes);
+                const double d = std::sqrt((t + 1.0) / 8.0);  // > 0 at every node
+                double sum = 0.0;
+                for (int n = 2; n <= mlp::kFarImages; ++n) {
+                    const double lo = std::pow(n - d, -m), hi = std::pow(n + d, -m);
+                    sum += comp == 0 ? lo - hi : lo + hi;
+                }
+                f[j] = comp == 0 ? sum / d : sum;
+            }
+            double a[kDeg + 1];
+            for (int i = 0; i <= kDeg; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < kNodes; ++j) acc += f[j] * std::cos(kPi * i * (j + 0.5) / kNodes);
+                a[i] = acc * (i == 0 ? 1.0 : 2.0) / kNodes;
+            }
+            // T_0 = 1, T_1 = t, T_{i+1} = 2 t T_i - T_{i-1}, as monomial coefficients
+            double p[kDeg + 1] = {}, tm[kDeg + 1] = {}, tc[kDeg + 1] = {}, tn[kDeg + 1];
+            tm[0] = 1.0;
+            tc[1] = 1.0;
+            p[0] = a[0];
+            p[1] = a[1];
+            for (int i = 2; i <= kDeg; ++i) {
+                for (int e = 0; e <= kDeg; ++e) tn[e] = (e > 0 ? 2.0 * tc[e - 1] : 0.0) - tm[e];
+                for (int e = 0; e <= kDeg; ++e) {
+                    tm[e] = tc[e];
+                    tc[e] = tn[e];
+                    p[e] += a[i] * tc[e];
+                }
+            }
+            for (int e = 0; e <= kDeg; ++e) bs.c[comp][k][kDeg - e] = (float)(b[k] * p[e]);
+        }
+    return bs;
+}
+
+const BandSeries &band_series() {
+    static const BandSeries bs = make_band_series();
+    return bs;
+}
+
+}  // namespace
+
 int launch_forces_learned(const double *pos, const double *mass, const double *eps, int64_t N, double L,
                           const steps_cyl_mlp *net, const int64_t *targets, int64_t n_tgt, int mode,
                           float *out_acc, float *out_pot, Workspace &ws, hipStream_t stream) {
@@ -311,6 +430,7 @@ int launch_forces_learned(const double *pos, const double *mass, const double *e
     a.c.L2f = (float)(L * L);
     a.c.m2Lf = (float)(-2.0 * L);
     a.c.n_img = 1;
+    a.bs = band_series();
     a.N = (int)N;
     a.n_tgt = (int)n_tgt;
     a.perm = nullptr;
@@ -423,6 +543,7 @@ __global__ __launch_bounds__(kBlock, 3) void forces_learned_pairwise_kernel(Pair
     __shared__ mlp::Packed P;
     __shared__ SrcRec tile[kOwn];
     __shared__ double jpart[kBlock / 64][4][kOwn];  // per wave, component, source
+    __shared__ BandSeries bands;
     const LearnedArgs &a = pa.la;
     const int meet = blockIdx.x / (kSubs * kSubs);
     const int si = (blockIdx.x / kSubs) % kSubs, sj = blockIdx.x % kSubs;
@@ -443,6 +564,7 @@ __global__ __launch_bounds__(kBlock, 3) void forces_learned_pairwise_kernel(Pair
     if ((int64_t)ta * kOwn >= pa.N) return;                   // no targets (whole workgroup)
     if (REACT && (int64_t)sb * kOwn >= pa.N) return;          // no sources: nothing to add
     mlp::load_packed(&P, a.P);
+    load_band_series(&bands, a.bs);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int col = lane & 31, h = lane >> 5;
@@ -499,18 +621,7 @@ __global__ __launch_bounds__(kBlock, 3) void forces_learned_pairwise_kernel(Pair
                 Rz = 0.f;
                 Rr = 0.f;
             }
-            uint64_t outside = __ballot(q.band && active);
-            while (outside) {
-                const int c = __builtin_ctzll(outside);
-                outside &= outside - 1;
-                const float dc = __shfl(q.d * a.invLf, c), rc = __shfl(q.r, c);
-                float tz, tr;
-                band_cooperative(dc, rc, tz, tr);
-                if (lane == c) {
-                    Rz = tz;
-                    Rr = tr;
-                }
-            }
+            band_outside(a, bands, q, active, Rz, Rr);
             const float rinv = q.rho > 0.f ? __builtin_amdgcn_rcpf(q.rho) : 0.f;
             const double Seff = (double)__builtin_fmaf(-Rr * a.invL2f, rinv, q.S);
             const double Fzeff = (double)__builtin_fmaf(-Rz, a.invL2f, q.Fz);
@@ -630,6 +741,7 @@ int launch_forces_learned_pairwise(const double *pos, const double *mass, const 
     a.c.L2f = (float)(L * L);
     a.c.m2Lf = (float)(-2.0 * L);
     a.c.n_img = 1;
+    a.bs = band_series();
     a.N = (int)N;
     a.n_tgt = (int)N;
     pa.rec = rec;

@@ -182,3 +182,31 @@ def test_long_target_lists_in_spatial_order_are_bitwise_exact(sc, net):
     torch.cuda.synchronize()
     assert torch.equal(full[:, tg], sub)
     assert torch.equal(fpot[tg], spot)
+
+
+def test_near_axis_pairs_take_the_band_series(sc, net):
+    # every pair closer than 0.05 L to the axis of the other: no pair is in the
+    # network's domain, and the kernels evaluate the band 2 <= |n| <= 1024 of
+    # each from its series in rho^2 (exact to FP32 rounding); the oracle sums
+    # the 2046 images directly.  The band is 5-20 % of these forces, so a
+    # missing series term (1e-5 of the band) or a wrong coefficient would
+    # exceed the 1e-6 bar, FP32 rounding (~1e-7) would not.
+    rng = np.random.default_rng(7)
+    N = 256
+    rr = 0.02 * np.sqrt(rng.random(N))
+    phi = 2.0 * math.pi * rng.random(N)
+    pos = np.stack([rr * np.cos(phi), rr * np.sin(phi), rng.random(N)])
+    mass = np.full(N, 1.0 / N)
+    eps = np.full(N, 1e-4)
+    p = synth.Particles(pos, mass, eps, 1.0)
+    d_pos, d_m, d_e = to_dev(p)
+    print("[case] near-axis learned N=256", flush=True)
+    acc, _ = sc.steps_cyl_forces_learned(d_pos, d_m, d_e, p.L, net, potential=False)
+    t = torch.arange(0, N, 3, dtype=torch.int64, device=d_pos.device)
+    acc_t, _ = sc.steps_cyl_forces_learned_ex(d_pos, d_m, d_e, p.L, net, targets=t, potential=False)
+    torch.cuda.synchronize()
+    ref = om.forces_learned(p.pos, p.mass, p.eps, p.L, net.params().astype(np.float64))
+    err = rel_err(acc, ref)
+    err_t = rel_err(acc_t, ref[:, t.cpu().numpy()])
+    print(f"near-axis band: pairwise max {err.max():.2e}, per-target max {err_t.max():.2e}")
+    assert err.max() <= 1e-6 and err_t.max() <= 1e-6
