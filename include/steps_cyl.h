@@ -251,7 +251,10 @@ int steps_cyl_forces_f64_ws(const double *pos, const double *mass, const double 
  * and b is a fixed analytic baseline: the images on each side replaced by a
  * uniform rod from 1.5 L to 1024.5 L, plus the first midpoint-rule
  * correction at 1.5 L.  The network domain is 0.05 <= rho/L <= 20; pairs
- * outside it use the exact image band.  Sign folding makes R_z odd and R_rho
+ * outside it use the exact image band (for rho/L < 0.05 evaluated from a
+ * convergent series in rho^2 whose image sums are held as polynomials in
+ * (d/L)^2, equal to the direct sum to FP32 rounding; beyond rho/L = 20 summed
+ * image by image).  Sign folding makes R_z odd and R_rho
  * even in d, so learned pair forces stay antisymmetric (momentum is
  * conserved).  This stands in for the paper's interpolated correction table
  * D(rho, z) (Sect. 2.2, eq. S1R2EwaldCorrectionTable) as the way to add the
