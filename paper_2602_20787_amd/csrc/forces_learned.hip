@@ -11,13 +11,14 @@
 // baseline, features, accumulation) for the even source and half 1 for the
 // odd one, and the wave then evaluates two network tiles of 32 pairs each
 // (32 targets x 1 source), the features crossing halves by one swap.  In a
-// tile, layer 1 and the activations run on the VALU, layers 2-4 as 8 MFMAs
-// each, layer 5 on the VALU with a cross-half sum.  Each half keeps its own
-// compensated sums; they are added at the end.  Pairs outside
-// the network's domain (rho/L < 0.05 or > 20) take the exact image band
-// instead; all 64 lanes share that sum (32 images each plus a butterfly
-// reduction), so a rare outside pair costs about 250 instructions instead
-// of a 2046-image serial loop in one lane.
+// tile, layer 1 runs on MFMA through the exact three-part BF16 split of its
+// FP32 inputs, layers 2-4 as 8 MFMAs each, the activations and layer 5 on
+// the VALU (layer 5 with a cross-half sum).  Each half keeps its own
+// compensated sums; they are added at the end.  Pairs outside the network's
+// domain take the exact image band instead: near the axis (rho/L < 0.05)
+// each lane evaluates its pair's band from a series (BandSeries, below);
+// beyond rho/L = 20 all 64 lanes share the direct sum of one pair (32 images
+// each plus a butterfly reduction).
 #include <cmath>
 
 #include "common.h"
