@@ -18,7 +18,8 @@ Secondary legs (each timed as the median of several runs after a warm-up):
     correction (every unordered pair once), the 144 x 128 correction tables
     (CIC, TSC) and the exact |n| <= 1024 sum (per-target kernel on a subset of
     targets, scaled to all targets), with accuracy against the FP64 |n| <= 1024
-    reference on 1024 targets;
+    reference on 1024 targets, beside that of the truncated sums |n| <= 1 and
+    |n| <= 8;
   * octree and table builds.
 
 Prints one JSON line.  ``value`` is G pair-interactions/s (N^2 / t / 1e9).
@@ -308,7 +309,8 @@ def learned_leg(args, dev):
     once), and the exact |n| <= 1024 sum and the learned correction with the
     per-target kernels on a subset of targets, scaled to all N targets (the
     per-target cost does not depend on the target).  Accuracy of each against
-    the FP64 |n| <= 1024 reference on 1024 targets (the first of the subset)."""
+    the FP64 |n| <= 1024 reference on 1024 targets (the first of the subset),
+    and of the exact sums truncated at |n| <= 1 and |n| <= 8 for comparison."""
     import numpy as np
     import torch
 
@@ -362,6 +364,7 @@ def learned_leg(args, dev):
     scale = N / k_sub
     ref, _ = sc.steps_cyl_forces_f64(pos, m, e, p.L, 1024, targets=acc_t, potential=False)
     a8, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=acc_t, potential=False)
+    a1, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 1, targets=acc_t, potential=False)
     torch.cuda.synchronize()
     r = ref.cpu().numpy()
 
@@ -386,6 +389,7 @@ def learned_leg(args, dev):
         "speedup_learned_pairwise_vs_exact1024_per_target": round(ms_xs * scale / ms_lp, 2),
         "speedup_learned_vs_exact1024_per_target_both": round(ms_xs / ms_ls, 2),
         "exact8_err": err(a8),
+        "exact1_err": err(a1),
         "err_targets": 1024, "subset_targets": k_sub,
         "table_144x128": {
             "cic_ms": round(ms_tab[1], 1), "tsc_ms": round(ms_tab[2], 1), "runs": args.secondary_runs,
