@@ -22,7 +22,8 @@ the per-target kernels of the table path); the tree path always computes
 every particle.  The potential is
 skipped except for ``exact`` with --potential.  Prints one JSON line: the
 path, sizes, milliseconds per call and pair interactions per second (for
-the direct paths).
+the direct paths), and with --check-targets K the error against the FP64
+reference on K sampled targets.
 """
 from __future__ import annotations
 
@@ -54,6 +55,9 @@ def main(argv=None):
     ap.add_argument("--quadrupole", action="store_true")
     ap.add_argument("--reps", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--check-targets", type=int, default=0,
+                    help="error against the FP64 reference (|n| <= n_img for exact, <= 1024 for the far-image "
+                         "paths) on this many sampled targets (0: no check)")
     args = ap.parse_args(argv)
 
     import numpy as np
@@ -128,6 +132,16 @@ def main(argv=None):
         row.update({"n_img": args.n_img, "pairwise": args.pairwise, "potential": args.potential})
     if args.path == "learned":
         row["pairwise"] = args.pairwise
+    if args.check_targets > 0 and args.path != "tree":
+        # the targets are particles 0..K-1 in order on every path here
+        pick = synth.target_sample(K, args.check_targets, seed=7)
+        ref, _ = sc.steps_cyl_forces_f64(pos, m, e, p.L, args.n_img if args.path == "exact" else 1024,
+                                         targets=torch.from_numpy(pick).to(dev), potential=False)
+        a = out[:, torch.from_numpy(pick).to(dev)].double().cpu().numpy()
+        r = ref.cpu().numpy()
+        err = np.linalg.norm(a - r, axis=0) / np.linalg.norm(r, axis=0)
+        row["err_vs_f64"] = {"targets": int(pick.shape[0]), "max": float(f"{err.max():.3e}"),
+                             "median": float(f"{np.median(err):.3e}")}
     print(json.dumps(row), flush=True)
 
 

@@ -84,6 +84,17 @@ def test_image_counts_without_potential(sc, n_img):
     check(a, None, a_ref, None)
 
 
+def test_far_image_count_of_the_learned_comparison(sc):
+    # |n| <= 1024 (the sum the far-image corrections are measured against) on
+    # the run-time image loop, three groups with a ragged one, with the
+    # potential; 256 sampled targets against the oracle
+    p = synth.cylinder_load(2100, seed=5)
+    a, pot = pairwise(sc, p.pos, p.mass, p.eps, p.L, 1024)
+    t = synth.target_sample(2100, 256, seed=1)
+    a_ref, p_ref = oracle.forces(p.pos, p.mass, p.eps, p.L, 1024, targets=t)
+    check(a[:, t], pot[t], a_ref, p_ref)
+
+
 def test_clustered_load_takes_the_spline_on_both_sides(sc):
     # 64 Plummer clumps: many pairs inside their softening length, across groups
     p = synth.clustered_load(6000, n_clumps=8, clump_frac=0.05, seed=3)

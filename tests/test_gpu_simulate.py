@@ -53,6 +53,18 @@ def test_profiling_driver_runs_each_path(capsys, argv):
     assert all(ms > 0 for ms in row["ms"])
 
 
+@pytest.mark.parametrize("argv,bar", [(["--path", "exact", "--pairwise", "--n-img", "1024"], 1e-5),
+                                      (["--path", "learned", "--pairwise"], 1e-4)])
+def test_profiling_driver_checks_against_the_f64_reference(capsys, argv, bar):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_20787_amd import run_kernel
+    run_kernel.main(argv + ["--N", "4096", "--reps", "1", "--check-targets", "128"])
+    row = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert row["err_vs_f64"]["targets"] == 128
+    assert row["err_vs_f64"]["max"] <= bar
+
+
 def test_stop_after_runs_a_prefix_of_the_schedule(sim, capsys):
     # the first 3 of 6 steps: the same step sizes and, with deterministic
     # forces and kicks, the same state as the full run at step 3
