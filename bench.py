@@ -17,7 +17,8 @@ Secondary legs (each timed as the median of several runs after a warm-up):
   * learned: at --learned-n particles (default 2^20), the learned far-image
     correction (every unordered pair once), the 144 x 128 correction tables
     (CIC, TSC) and the exact |n| <= 1024 sum (per-target kernel on a subset of
-    targets, scaled to all targets), with accuracy against the FP64 |n| <= 1024
+    targets, scaled to all targets, and on the pairwise schedule at 2^19
+    particles, scaled by N^2), with accuracy against the FP64 |n| <= 1024
     reference on 1024 targets, beside that of the truncated sums |n| <= 1 and
     |n| <= 8;
   * octree and table builds.
@@ -308,7 +309,9 @@ def learned_leg(args, dev):
     144 x 128 correction tables over all particles (every unordered pair
     once), and the exact |n| <= 1024 sum and the learned correction with the
     per-target kernels on a subset of targets, scaled to all N targets (the
-    per-target cost does not depend on the target).  Accuracy of each against
+    per-target cost does not depend on the target); the exact |n| <= 1024 sum
+    also on the learned path's pairwise schedule at args.exact1024_pairwise_n
+    particles, scaled by (N / n)^2.  Accuracy of each against
     the FP64 |n| <= 1024 reference on 1024 targets (the first of the subset),
     and of the exact sums truncated at |n| <= 1 and |n| <= 8 for comparison."""
     import numpy as np
@@ -362,6 +365,27 @@ def learned_leg(args, dev):
                      args.learned_runs, stream)
     print(f"[bench] exact |n|<=1024 per-target {k_sub} targets: {ms_xs:.1f} ms", file=sys.stderr, flush=True)
     scale = N / k_sub
+    # the exact |n| <= 1024 sum on the pairwise schedule of the learned path: one call at n_pw
+    # particles (groups of 1024 at every N up to 2^21, so the meetings are the same and the work
+    # grows as N^2), scaled to N
+    n_pw = min(N, args.exact1024_pairwise_n)
+    xpw = None
+    if n_pw > 0:
+        q = synth.cylinder_load(n_pw, seed=0)
+        qpos = torch.from_numpy(q.pos).to(dev)
+        qm = torch.from_numpy(q.mass).to(dev)
+        qe = torch.from_numpy(q.eps).to(dev)
+        acc_q = torch.empty((3, n_pw), dtype=torch.float32, device=dev)
+        w = min(n_pw, 4096)
+        sc.steps_cyl_forces(qpos[:, :w].contiguous(), qm[:w].contiguous(), qe[:w].contiguous(), q.L, 1024,
+                            potential=False)  # code objects
+        ms_pw, _ = timed(lambda: sc.steps_cyl_forces(qpos, qm, qe, q.L, 1024, out_acc=acc_q, potential=False,
+                                                     stream=stream), 1, stream)
+        ms_pw_n = ms_pw * (float(N) / n_pw) ** 2
+        xpw = {"N_measured": n_pw, "ms_measured": round(ms_pw, 1), "ms_scaled_to_N": round(ms_pw_n, 1),
+               "G_pairs_per_s": round(float(n_pw) * n_pw / (ms_pw * 1e-3) / 1e9, 3)}
+        print(f"[bench] exact |n|<=1024 pairwise N={n_pw}: {ms_pw / 1e3:.2f} s", file=sys.stderr, flush=True)
+        del qpos, qm, qe, acc_q
     ref, _ = sc.steps_cyl_forces_f64(pos, m, e, p.L, 1024, targets=acc_t, potential=False)
     a8, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 8, targets=acc_t, potential=False)
     a1, _ = sc.steps_cyl_forces_ex(pos, m, e, p.L, 1, targets=acc_t, potential=False)
@@ -376,7 +400,9 @@ def learned_leg(args, dev):
         "workload": f"stereographic cylinder load N={N} (seed 0): exact |n|<=1 + network (or 144x128 "
                     f"table) for 2<=|n|<=1024 over all particles (each unordered pair once), against "
                     f"exact |n|<=1024; the per-target times are measured on {k_sub} random targets and "
-                    f"scaled by N/{k_sub} (per-target cost is the same for every target)",
+                    f"scaled by N/{k_sub} (per-target cost is the same for every target)"
+                    + (f"; the exact |n|<=1024 sum on the pairwise schedule is timed at N={n_pw} and scaled "
+                       f"by (N/{n_pw})^2" if n_pw > 0 else ""),
         "learned_pairwise": {"ms": round(ms_lp, 1), "runs": len(ms_lp_all),
                              "G_pairs_per_s": round(pairs / (ms_lp * 1e-3) / 1e9, 3),
                              "err": err(acc_lp[:, acc_t])},
@@ -388,6 +414,9 @@ def learned_leg(args, dev):
                                  "err_fp32_vs_fp64": err(acc_xs[:, :1024])},
         "speedup_learned_pairwise_vs_exact1024_per_target": round(ms_xs * scale / ms_lp, 2),
         "speedup_learned_vs_exact1024_per_target_both": round(ms_xs / ms_ls, 2),
+        "exact1024_pairwise": xpw,
+        "speedup_learned_pairwise_vs_exact1024_pairwise": (round(xpw["ms_scaled_to_N"] / ms_lp, 2)
+                                                            if xpw else None),
         "exact8_err": err(a8),
         "exact1_err": err(a1),
         "err_targets": 1024, "subset_targets": k_sub,
@@ -521,6 +550,9 @@ def main():
                     help="particles of the far-image comparison (0 skips it)")
     ap.add_argument("--learned-subset", type=int, default=16384,
                     help="targets of the per-target far-image timings (scaled to all targets)")
+    ap.add_argument("--exact1024-pairwise-n", type=int, default=1 << 19,
+                    help="particles at which the exact |n|<=1024 sum is timed on the pairwise schedule, "
+                         "scaled to --learned-n by (N/n)^2 (0 skips it)")
     ap.add_argument("--learned-runs", type=int, default=3,
                     help="timed runs of the learned and exact |n|<=1024 evaluations (median)")
     ap.add_argument("--secondary-runs", type=int, default=5,
