@@ -6,8 +6,9 @@ counts are bit-exact (both sides take the cell and acceptance decisions in
 FP64 with the same operations); cell masses and centres of mass to FP64
 summation-order round-off; forces to 2e-5 relative (FP32 pair arithmetic
 and FP32 table nodes, as for the tabulated scheme); theta = 0 reproduces
-the direct tabulated kernel to FP32 summation-order round-off (2e-5: each
-side is within 1e-5 of FP64 and sums the same pairs in another order); the radial
+the direct tabulated kernel to FP32 summation-order round-off (2e-5: the
+same pairs summed in another order) and the oracle's FP64 tabulated scheme
+to the tabulated path's own bar against it (2e-5); the radial
 correction to 1e-5 of the mean force (it is a mean of differences of FP32
 forces).
 """
@@ -74,10 +75,18 @@ def test_zero_opening_angle_is_the_direct_kernel(sc):
     a = sc.steps_cyl_tree_forces(t, pos, m, e, p.L, R, tab, 1, 0.0, 0.4, 0.8)
     d, _ = sc.steps_cyl_forces_table(pos, m, e, p.L, tab, order=1, potential=False)
     torch.cuda.synchronize()
-    err = rel(a.double().cpu().numpy(), d.double().cpu().numpy())
-    # the same pairs summed in another order: both within 1e-5 of FP64
+    a_np = a.double().cpu().numpy()
+    err = rel(a_np, d.double().cpu().numpy())
+    # the same pairs summed in another order
     print(f"theta=0 vs direct kernel: max {err.max():.2e}")
     assert err.max() <= 2e-5, err.max()
+    # and the oracle's FP64 tabulated scheme on sampled targets, at the
+    # tabulated path's own bar against it
+    tg = synth.target_sample(p.N, 64, seed=3)
+    ref = ot.forces_table(p.pos, p.mass, p.eps, p.L, ot.Table(32, 40, 6.5), 1, targets=tg)
+    e_ref = rel(a_np[:, tg], ref)
+    print(f"theta=0 vs oracle tabulated scheme: max {e_ref.max():.2e}")
+    assert e_ref.max() <= 2e-5, e_ref.max()
     n_cells, n_c, n_p = sc.steps_cyl_tree_info(t)
     assert n_c == 0 and n_p == p.N * p.N
     t.close()
