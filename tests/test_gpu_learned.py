@@ -99,8 +99,9 @@ def test_learned_momentum_and_subset(sc, net):
 @pytest.mark.parametrize("N", [2, 129, 1000, 5000])
 def test_pairwise_learned_matches_per_target_and_oracle(sc, net, N):
     # steps_cyl_forces_learned evaluates every unordered pair once (groups of
-    # 128: one group, ragged tails, odd and even group counts); the per-target
-    # kernel and the oracle of the learned scheme are the references
+    # 1024 in sub-groups of 128: one group with ragged sub-groups, and an odd
+    # group count); the per-target kernel and the oracle of the learned scheme
+    # are the references
     p = load_with_axis_line(N, seed=70 + N) if N >= 20 else synth.cylinder_load(N, seed=70)
     pos, m, e = to_dev(p)
     print(f"[case] pairwise learned N={N}", flush=True)
@@ -118,6 +119,23 @@ def test_pairwise_learned_matches_per_target_and_oracle(sc, net, N):
     # off-domain pairs sums its images in a sign-dependent order)
     mom = np.abs((p.mass[None, :] * f).sum(axis=1)) / (p.mass[None, :] * np.abs(f)).sum(axis=1)
     assert mom.max() <= 1e-5
+
+
+def test_pairwise_learned_many_groups_sampled(sc, net):
+    # 65 groups of 1024 after the spatial sort (an odd count, the last of 37
+    # particles: one ragged sub-group), 2080 meetings; the near-axis particles
+    # and 20 sampled targets against the oracle of the learned scheme
+    N = (1 << 16) + 37
+    p = load_with_axis_line(N, seed=123)
+    pos, m, e = to_dev(p)
+    print(f"[case] pairwise learned N={N}", flush=True)
+    full, _ = sc.steps_cyl_forces_learned(pos, m, e, p.L, net, potential=False)
+    torch.cuda.synchronize()
+    t = np.unique(np.concatenate([np.arange(4), synth.target_sample(N, 20, seed=4)]))
+    ref = om.forces_learned(p.pos, p.mass, p.eps, p.L, net.params().astype(np.float64), targets=t)
+    err = rel_err(full[:, torch.from_numpy(t).cuda()], ref)
+    print(f"max {err.max():.2e} over {t.size} targets")
+    assert err.max() <= TOL
 
 
 @pytest.mark.parametrize("N", [5000, 9000])
